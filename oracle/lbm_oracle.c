@@ -1,0 +1,605 @@
+/*
+ * Reference oracle for the D2Q9 multiple-relaxation-time lattice Boltzmann step with the
+ * local curved slip boundary of Wang, Tao, Hu, Zhang and Lu, "Curved boundary conditions of
+ * the lattice Boltzmann method for simulating microgaseous flows in the slip regime"
+ * (arXiv:2012.14707).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load this library.  The GPU library never links, includes or calls it,
+ * and it shares no code, header, table or constant with the GPU library.
+ *
+ * What it is: a plain, slow, literal implementation of the method, written from the paper:
+ *   - macroscopic fields, Eq. (FluidMacr);
+ *   - equilibrium, Eq. (LBEequi);
+ *   - Guo forcing, Eq. (LBEforce) and the moment-space forcing F = M^-1 (I - S/2) M Fbar;
+ *   - moment-space collision, Eq. (MomentPost), with the printed transformation matrix M
+ *     (Sec. II) and its inverse obtained by Gauss-Jordan elimination;
+ *   - streaming f_i(x + c_i, t + 1) = f'_i(x, t);
+ *   - the boundary scheme of Eq. (EqNewBDSC) for every wall link, with its coefficients
+ *     taken straight from r, l and the distance ratio gamma (no pre-folded coefficients);
+ *   - the diffuse-bounce-back scheme of Eq. (EqDBB), coded separately, for the Remark 2 check;
+ *   - the parameter prescription of Sec. III.B: Eq. (tKnrela) for tau_s, Eq. (Eqexlva) for l,
+ *     Eqs. (SliCoeffrtsr)/(NSliCoertsr) for r, Eq. (NSliCoertstq) for the uniform tau_q,
+ *     Eq. (EqECond) for the upper bound on E, and the clamp l := 0 when l < -0.4 (end of
+ *     Sec. III.B).
+ *
+ * Precision: every lattice quantity is held in x87 extended precision (long double, 64-bit
+ * significand), i.e. at least fp64.  Populations are O(1) while the slip-flow velocities of
+ * these workloads are 1e-5 .. 1e-2, so an fp64 evaluation of the literal population form
+ * carries rounding noise of order 1e-17 / 1e-5 relative to the velocity per step; the extra
+ * 11 bits keep the oracle's own noise well below the parity tolerances it is used to judge.
+ *
+ * Lattice units: delta_x = delta_t = 1, c = 1, c_s^2 = 1/3.
+ *
+ * Readings where the paper is silent or ambiguous (all documented with the design notes):
+ *   - Eq. (LBEforce) prints c_j . a in the first term; the index is read as c_i.
+ *   - The Maxwell-diffuse equilibrium f_i^eq(rho_f, .) of Eq. (EqNewBDSC) is evaluated at the
+ *     boundary node's own (half-force) velocity u(x_f, t) by default ("node" reading): this is
+ *     the reading under which the paper's analysis, Eqs. (NumerSana)-(CoeC) and the slip
+ *     relation Eq. (EqMiSlip), hold.  The literal wall-velocity reading is available as
+ *     diffuse = WALL.
+ *   - f_{ibar}(x_f, t) in Eq. (EqNewBDSC) is the pre-collision population at x_f at time t.
+ *   - Solid nodes are neither updated nor read.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_FP64
+/* fp64 build, used only to show the rounding floor of the literal population form */
+typedef double real;
+#else
+typedef long double real;
+#endif
+
+/* ---------------------------------------------------------------- D2Q9 lattice, Eq. (Eq3) */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+/* ibar: e_ibar = -e_i */
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+static real weight(int i)
+{
+    if (i == 0) return 4.0L / 9.0L;
+    if (i <= 4) return 1.0L / 9.0L;
+    return 1.0L / 36.0L;
+}
+
+/* Transformation matrix M exactly as printed in Sec. II (Lallemand-Luo form, c = 1);
+ * moment order (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy). */
+static const int MMAT[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1},
+};
+
+enum { ORA_OK = 0, ORA_E_INVAL = -1, ORA_E_NOMEM = -2, ORA_E_GEOMETRY = -4, ORA_E_PARAM = -5,
+       ORA_E_STATE = -7 };
+
+/* Modes.  These integers are the oracle's own; callers map their names onto them. */
+enum { L_PAPER = 0, L_CLAMP_NEG = 1, L_ZERO = 2, L_GAMMA = 3, L_TWO_GAMMA = 4, L_GAMMA2 = 5,
+       L_GAMMA2_PLUS_GAMMA = 6, L_FIXED = 7 };
+enum { R_FROM_LEFF = 0, R_PAPER = 1, R_FIXED = 2 };
+enum { DIFFUSE_NODE = 0, DIFFUSE_WALL = 1 };
+enum { BC_NEW = 0, BC_DBB = 1 };
+
+/* Inputs of the problem statement.  NaN in L1, L2, E and <= 0 in the overrides select the
+ * paper's prescription. */
+typedef struct {
+    int32_t nx, ny, periodic_x, periodic_y;
+    double kn, h;
+    double sigma, L1, L2, E;
+    double tau_rho, tau_e, tau_eps, tau_j;
+    double tau_s_override, tau_q_override, r_override, l_override;
+    int32_t l_mode, r_mode, diffuse, bc_kind;
+    double ax, ay, rho0;
+} ora_params;
+
+/* Derived global parameters (reported back to the caller in double). */
+typedef struct {
+    double tau_s, tau_q, E, E_max, L1, L2, nu;
+    int32_t n_clamped, n_nonconvex;
+} ora_globals;
+
+typedef struct {
+    ora_params p;
+    int nx, ny;
+    int64_t n;
+    uint8_t *solid;
+    int32_t *linkidx;          /* n * 9: link index for (site, direction toward the wall) or -1 */
+    int64_t nlinks;
+    real *lr, *ll, *lg, *lubx, *luby; /* per link: r, l, gamma, wall velocity */
+    int32_t *ldir;
+    real *f, *fpost, *fnew;    /* n * 9 each */
+    real *ux_prev, *uy_prev;
+    real s[9];
+    real minv[9][9];
+    real tau_s, tau_q;
+    int64_t steps_since_init;
+    real last_link_flux;
+} ora_ctx;
+
+/* ------------------------------------------------------------ parameter prescription */
+
+static const real PI_L = 3.141592653589793238462643383279502884L;
+
+static real sq6pi(void) { return sqrtl(6.0L / PI_L); }
+
+/* Eq. (tKnrela): tau_s = 1/2 + sqrt(6/pi) Kn H / dx, dx = 1. */
+static real tau_s_from_kn(real kn, real h) { return 0.5L + sq6pi() * kn * h; }
+
+/* Sec. IV: L1 = (2 - sigma)(1 - 0.1817 sigma)/sigma, L2 = 1/pi + L1^2/2. */
+static real l1_poiseuille(real sigma) { return (2.0L - sigma) * (1.0L - 0.1817L * sigma) / sigma; }
+static real l2_poiseuille(real l1) { return 1.0L / PI_L + l1 * l1 / 2.0L; }
+
+/* Eq. (EqECond): upper bound on E from tau_q > 1/2. */
+static real e_max(real ts, real L1, real L2)
+{
+    return (PI_L * ts * L2 - 3.0L * sqrtl(PI_L / 6.0L) * L1) * (2.0L * ts - 1.0L) / (12.0L * ts) - 0.5L;
+}
+
+/* Eq. (NSliCoertstq): the uniform tau_q. */
+static real tau_q_uniform(real ts, real L1, real L2, real E)
+{
+    real num = (2.0L * ts - 1.0L) * (ts * sqrtl(6.0L * PI_L) * L2 - L1) - 2.0L * sq6pi() * ts * (1.0L + 6.0L * E);
+    real den = 8.0L * sq6pi() * ts + 4.0L * L1 * (2.0L * ts - 1.0L);
+    return num / den;
+}
+
+/* Eq. (Eqexlva): l(gamma) with the constant E. */
+static real l_of_gamma(real g, real ts, real L1, real E)
+{
+    real a = sq6pi();
+    return (a * g * g + g * (2.0L * ts - 1.0L) * (L1 + a)) / (a * (2.0L * ts - 1.0L)) + E;
+}
+
+/* Eq. (SliCoeffrtsr): r for a given l. */
+static real r_of_l(real l, real ts, real L1)
+{
+    real a = sq6pi();
+    return a * ts * (1.0L + l) / (L1 * (2.0L * ts - 1.0L) + a * ts * (1.0L + l));
+}
+
+/* Eq. (NSliCoertsr): r as a function of gamma once l follows Eq. (Eqexlva). */
+static real r_of_gamma(real g, real ts, real L1, real E)
+{
+    real a = sq6pi();
+    real br = g * g + g * (2.0L * ts - 1.0L) + (1.0L + E) * (2.0L * ts - 1.0L);
+    real num = L1 * ts * g * (2.0L * ts - 1.0L) + a * ts * br;
+    real den = L1 * (2.0L * ts - 1.0L) * ((2.0L + g) * ts - 1.0L) + a * ts * br;
+    return num / den;
+}
+
+/* Eq. (SliCoeffrtstq): tau_q for given gamma and l (used only by the identity checks). */
+double ora_tau_q_general(double g_, double l_, double ts_, double L1_, double L2_)
+{
+    real g = g_, l = l_, ts = ts_, L1 = L1_, L2 = L2_, a = sq6pi();
+    real num = L1 * (2.0L * ts - 1.0L) * (2.0L * ts * (6.0L * g - 1.0L) + 1.0L)
+             + a * ts * (L2 * PI_L * (2.0L * ts - 1.0L) * (2.0L * ts - 1.0L) + 12.0L * g * g
+                         + 2.0L * (2.0L * ts - 1.0L) * (6.0L * g - 6.0L * l - 1.0L));
+    real den = 4.0L * (2.0L * ts - 1.0L) * (2.0L * a * ts + L1 * (2.0L * ts - 1.0L));
+    return (double)(num / den);
+}
+
+double ora_l_of_gamma(double g, double ts, double L1, double E) { return (double)l_of_gamma(g, ts, L1, E); }
+double ora_r_of_l(double l, double ts, double L1) { return (double)r_of_l(l, ts, L1); }
+double ora_r_of_gamma(double g, double ts, double L1, double E) { return (double)r_of_gamma(g, ts, L1, E); }
+double ora_tau_q_uniform(double ts, double L1, double L2, double E) { return (double)tau_q_uniform(ts, L1, L2, E); }
+double ora_e_max(double ts, double L1, double L2) { return (double)e_max(ts, L1, L2); }
+
+static int is_set(double v) { return !(v != v) && v > 0.0; }
+
+/* Global parameters: tau_s, L1, L2, E and tau_q. */
+static int derive_globals(const ora_params *p, real *ts, real *L1, real *L2, real *E, real *Emax, real *tq)
+{
+    *ts = is_set(p->tau_s_override) ? (real)p->tau_s_override : tau_s_from_kn(p->kn, p->h);
+    if (!(*ts > 0.5L)) return ORA_E_PARAM;
+    real sig = p->sigma;
+    *L1 = (p->L1 != p->L1) ? l1_poiseuille(sig) : (real)p->L1;
+    *L2 = (p->L2 != p->L2) ? l2_poiseuille(*L1) : (real)p->L2;
+    *Emax = e_max(*ts, *L1, *L2);
+    if (p->E != p->E) {
+        /* Reading: the paper uses E = -0.65 (and -0.68) and asks that E respect Eq. (EqECond);
+         * take -0.65 unless the bound forces a smaller value, keeping a 0.05 margin. */
+        real cand = *Emax - 0.05L;
+        *E = (cand < -0.65L) ? cand : -0.65L;
+    } else {
+        *E = p->E;
+    }
+    *tq = is_set(p->tau_q_override) ? (real)p->tau_q_override : tau_q_uniform(*ts, *L1, *L2, *E);
+    if (!(*tq > 0.5L)) return ORA_E_PARAM;
+    return ORA_OK;
+}
+
+/* Per-link l and r under the selected modes. */
+static void derive_link(const ora_params *p, real g, real ts, real L1, real E, real *l_raw, real *l_eff, real *r)
+{
+    real lr;
+    switch (p->l_mode) {
+    case L_ZERO: lr = 0.0L; break;
+    case L_GAMMA: lr = g; break;
+    case L_TWO_GAMMA: lr = 2.0L * g; break;
+    case L_GAMMA2: lr = g * g; break;
+    case L_GAMMA2_PLUS_GAMMA: lr = g * g + g; break;
+    case L_FIXED: lr = p->l_override; break;
+    default: lr = l_of_gamma(g, ts, L1, E); break;
+    }
+    real le = lr;
+    if (p->l_mode == L_PAPER && lr < -0.4L) le = 0.0L;       /* clamp at the end of Sec. III.B */
+    if (p->l_mode == L_CLAMP_NEG && lr < 0.0L) le = 0.0L;    /* stability fallback */
+    *l_raw = lr;
+    *l_eff = le;
+    if (p->r_mode == R_FIXED) *r = p->r_override;
+    else if (p->r_mode == R_PAPER) *r = r_of_gamma(g, ts, L1, E);
+    else *r = r_of_l(le, ts, L1);
+}
+
+/* Exported precompute: globals plus, per link, (l_raw, l_eff, r). */
+int ora_derive(const ora_params *p, int64_t nlinks, const double *q, ora_globals *out, double *link_out)
+{
+    real ts, L1, L2, E, Emax, tq;
+    int st = derive_globals(p, &ts, &L1, &L2, &E, &Emax, &tq);
+    out->tau_s = (double)ts; out->tau_q = (double)tq; out->E = (double)E; out->E_max = (double)Emax;
+    out->L1 = (double)L1; out->L2 = (double)L2; out->nu = (double)((ts - 0.5L) / 3.0L);
+    out->n_clamped = 0; out->n_nonconvex = 0;
+    if (st != ORA_OK) return st;
+    for (int64_t k = 0; k < nlinks; ++k) {
+        real lr, le, r, g = q[k];
+        derive_link(p, g, ts, L1, E, &lr, &le, &r);
+        if (le != lr) out->n_clamped++;
+        real lo = 2.0L * g - 1.0L; if (lo < 0.0L) lo = 0.0L;
+        if (le < lo || le > 2.0L * g) out->n_nonconvex++;
+        if (link_out) {
+            link_out[3 * k + 0] = (double)lr;
+            link_out[3 * k + 1] = (double)le;
+            link_out[3 * k + 2] = (double)r;
+        }
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------------ lattice helpers */
+
+/* Equilibrium, Eq. (LBEequi), with c_s^2 = 1/3. */
+static real feq(int i, real rho, real ux, real uy)
+{
+    const real cs2 = 1.0L / 3.0L;
+    real cu = CX[i] * ux + CY[i] * uy;
+    real uu = ux * ux + uy * uy;
+    return weight(i) * rho * (1.0L + cu / cs2 + cu * cu / (2.0L * cs2 * cs2) - uu / (2.0L * cs2));
+}
+
+/* Gauss-Jordan inverse of the printed M (partial pivoting), once per context. */
+static int invert_m(real out[9][9])
+{
+    real a[9][18];
+    for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 18; ++j)
+            a[i][j] = (j < 9) ? (real)MMAT[i][j] : (real)((j - 9) == i);
+    for (int c = 0; c < 9; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 9; ++r)
+            if (fabsl(a[r][c]) > fabsl(a[piv][c])) piv = r;
+        if (a[piv][c] == 0.0L) return -1;
+        if (piv != c)
+            for (int j = 0; j < 18; ++j) { real t = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = t; }
+        real d = a[c][c];
+        for (int j = 0; j < 18; ++j) a[c][j] /= d;
+        for (int r = 0; r < 9; ++r) {
+            if (r == c) continue;
+            real m = a[r][c];
+            if (m == 0.0L) continue;
+            for (int j = 0; j < 18; ++j) a[r][j] -= m * a[c][j];
+        }
+    }
+    for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 9; ++j) out[i][j] = a[i][9 + j];
+    return 0;
+}
+
+/* Neighbour of site (x, y) along (dx, dy); -1 when it leaves a non-periodic domain. */
+static int64_t neighbour(const ora_ctx *o, int x, int y, int dx, int dy)
+{
+    int xn = x + dx, yn = y + dy;
+    if (xn < 0 || xn >= o->nx) {
+        if (!o->p.periodic_x) return -1;
+        xn = (xn + o->nx) % o->nx;
+    }
+    if (yn < 0 || yn >= o->ny) {
+        if (!o->p.periodic_y) return -1;
+        yn = (yn + o->ny) % o->ny;
+    }
+    return (int64_t)yn * o->nx + xn;
+}
+
+/* Half-force macroscopic fields, Eq. (FluidMacr), delta_t = 1. */
+static void macro(const ora_ctx *o, const real *f, real *rho, real *ux, real *uy)
+{
+    real r = 0.0L, jx = 0.0L, jy = 0.0L;
+    for (int i = 0; i < 9; ++i) { r += f[i]; jx += CX[i] * f[i]; jy += CY[i] * f[i]; }
+    *rho = r;
+    *ux = (jx + 0.5L * r * (real)o->p.ax) / r;
+    *uy = (jy + 0.5L * r * (real)o->p.ay) / r;
+}
+
+/* Collision in moment space, Eqs. (LBEColli), (LBEforce), (MomentPost). */
+static void collide(const ora_ctx *o, const real *f, real *fp, real *rho_o, real *ux_o, real *uy_o)
+{
+    const real cs2 = 1.0L / 3.0L;
+    real rho, ux, uy;
+    macro(o, f, &rho, &ux, &uy);
+    real ax = o->p.ax, ay = o->p.ay;
+    real fe[9], fb[9], m[9], me[9], mf[9], mp[9];
+    for (int i = 0; i < 9; ++i) {
+        fe[i] = feq(i, rho, ux, uy);
+        real ca = CX[i] * ax + CY[i] * ay;
+        real cu = CX[i] * ux + CY[i] * uy;
+        real ua = ux * ax + uy * ay;
+        /* u a : (c_i c_i - c_s^2 I) = (c_i.u)(c_i.a) - c_s^2 (u.a) */
+        fb[i] = weight(i) * rho * (ca / cs2 + (cu * ca - cs2 * ua) / (cs2 * cs2));
+    }
+    for (int k = 0; k < 9; ++k) {
+        m[k] = me[k] = mf[k] = 0.0L;
+        for (int j = 0; j < 9; ++j) {
+            m[k] += MMAT[k][j] * f[j];
+            me[k] += MMAT[k][j] * fe[j];
+            mf[k] += MMAT[k][j] * fb[j];
+        }
+        mp[k] = m[k] - o->s[k] * (m[k] - me[k]) + (1.0L - o->s[k] / 2.0L) * mf[k];
+    }
+    for (int i = 0; i < 9; ++i) {
+        real acc = 0.0L;
+        for (int k = 0; k < 9; ++k) acc += o->minv[i][k] * mp[k];
+        fp[i] = acc;
+    }
+    *rho_o = rho; *ux_o = ux; *uy_o = uy;
+}
+
+/* ------------------------------------------------------------------------ lifecycle */
+
+void ora_destroy(ora_ctx *o)
+{
+    if (!o) return;
+    free(o->solid); free(o->linkidx);
+    free(o->lr); free(o->ll); free(o->lg); free(o->lubx); free(o->luby); free(o->ldir);
+    free(o->f); free(o->fpost); free(o->fnew);
+    free(o->ux_prev); free(o->uy_prev);
+    free(o);
+}
+
+/* Rest state f_i = w_i rho0 at fluid nodes. */
+int ora_init_rest(ora_ctx *o)
+{
+    for (int64_t s = 0; s < o->n; ++s)
+        for (int i = 0; i < 9; ++i) o->f[s * 9 + i] = o->solid[s] ? 0.0L : weight(i) * (real)o->p.rho0;
+    o->steps_since_init = 0;
+    return ORA_OK;
+}
+
+/* State from fields: f = f^eq(rho, u - a/2) so that the half-force velocity equals u. */
+int ora_init_fields(ora_ctx *o, const double *rho, const double *ux, const double *uy)
+{
+    for (int64_t s = 0; s < o->n; ++s) {
+        for (int i = 0; i < 9; ++i) {
+            if (o->solid[s]) { o->f[s * 9 + i] = 0.0L; continue; }
+            o->f[s * 9 + i] = feq(i, rho[s], (real)ux[s] - 0.5L * (real)o->p.ax, (real)uy[s] - 0.5L * (real)o->p.ay);
+        }
+    }
+    o->steps_since_init = 0;
+    return ORA_OK;
+}
+
+/* Links: (x, y) of the fluid node, dir = direction from the fluid node toward the wall
+ * (the paper's ibar), q = distance ratio gamma in (0, 1], (ubx, uby) = wall velocity at x_b. */
+int ora_create(const ora_params *p, const uint8_t *solid, int64_t nlinks, const int32_t *lx, const int32_t *ly,
+               const int32_t *ldir, const double *q, const double *ubx, const double *uby,
+               ora_globals *g, ora_ctx **out)
+{
+    *out = NULL;
+    if (p->nx <= 0 || p->ny <= 0 || p->rho0 <= 0.0) return ORA_E_INVAL;
+    ora_ctx *o = (ora_ctx *)calloc(1, sizeof(ora_ctx));
+    if (!o) return ORA_E_NOMEM;
+    o->p = *p;
+    o->nx = p->nx; o->ny = p->ny; o->n = (int64_t)p->nx * p->ny;
+    o->solid = (uint8_t *)malloc((size_t)o->n);
+    o->linkidx = (int32_t *)malloc(sizeof(int32_t) * 9 * (size_t)o->n);
+    o->nlinks = nlinks;
+    size_t nl = (size_t)(nlinks > 0 ? nlinks : 1);
+    o->lr = malloc(sizeof(real) * nl); o->ll = malloc(sizeof(real) * nl); o->lg = malloc(sizeof(real) * nl);
+    o->lubx = malloc(sizeof(real) * nl); o->luby = malloc(sizeof(real) * nl);
+    o->ldir = malloc(sizeof(int32_t) * nl);
+    o->f = malloc(sizeof(real) * 9 * (size_t)o->n);
+    o->fpost = malloc(sizeof(real) * 9 * (size_t)o->n);
+    o->fnew = malloc(sizeof(real) * 9 * (size_t)o->n);
+    o->ux_prev = malloc(sizeof(real) * (size_t)o->n);
+    o->uy_prev = malloc(sizeof(real) * (size_t)o->n);
+    if (!o->solid || !o->linkidx || !o->lr || !o->ll || !o->lg || !o->lubx || !o->luby || !o->ldir || !o->f ||
+        !o->fpost || !o->fnew || !o->ux_prev || !o->uy_prev) {
+        ora_destroy(o);
+        return ORA_E_NOMEM;
+    }
+    memcpy(o->solid, solid, (size_t)o->n);
+    for (int64_t s = 0; s < 9 * o->n; ++s) o->linkidx[s] = -1;
+
+    real ts, L1, L2, E, Emax, tq;
+    int st = derive_globals(p, &ts, &L1, &L2, &E, &Emax, &tq);
+    g->tau_s = (double)ts; g->tau_q = (double)tq; g->E = (double)E; g->E_max = (double)Emax;
+    g->L1 = (double)L1; g->L2 = (double)L2; g->nu = (double)((ts - 0.5L) / 3.0L);
+    g->n_clamped = 0; g->n_nonconvex = 0;
+    if (st != ORA_OK) { ora_destroy(o); return st; }
+    o->tau_s = ts; o->tau_q = tq;
+
+    for (int64_t k = 0; k < nlinks; ++k) {
+        int x = lx[k], y = ly[k], d = ldir[k];
+        if (x < 0 || x >= o->nx || y < 0 || y >= o->ny || d < 1 || d > 8) { ora_destroy(o); return ORA_E_GEOMETRY; }
+        if (!(q[k] > 0.0 && q[k] <= 1.0)) { ora_destroy(o); return ORA_E_GEOMETRY; }
+        int64_t s = (int64_t)y * o->nx + x;
+        int64_t nb = neighbour(o, x, y, CX[d], CY[d]);
+        if (o->solid[s] || nb < 0 || !o->solid[nb]) { ora_destroy(o); return ORA_E_GEOMETRY; }
+        if (o->linkidx[s * 9 + d] >= 0) { ora_destroy(o); return ORA_E_GEOMETRY; }
+        o->linkidx[s * 9 + d] = (int32_t)k;
+        real lr, le, r;
+        derive_link(p, q[k], ts, L1, E, &lr, &le, &r);
+        if (le != lr) g->n_clamped++;
+        real lo = 2.0L * q[k] - 1.0L; if (lo < 0.0L) lo = 0.0L;
+        if (le < lo || le > 2.0L * q[k]) g->n_nonconvex++;
+        o->lr[k] = r; o->ll[k] = le; o->lg[k] = q[k];
+        o->lubx[k] = ubx ? ubx[k] : 0.0; o->luby[k] = uby ? uby[k] : 0.0;
+        o->ldir[k] = d;
+    }
+    /* Every fluid node must see either a fluid neighbour or a wall link in each direction. */
+    for (int y = 0; y < o->ny; ++y)
+        for (int x = 0; x < o->nx; ++x) {
+            int64_t s = (int64_t)y * o->nx + x;
+            if (o->solid[s]) continue;
+            for (int d = 1; d < 9; ++d) {
+                int64_t nb = neighbour(o, x, y, CX[d], CY[d]);
+                if (nb < 0) { ora_destroy(o); return ORA_E_GEOMETRY; }
+                if (o->solid[nb] && o->linkidx[s * 9 + d] < 0) { ora_destroy(o); return ORA_E_GEOMETRY; }
+            }
+        }
+
+    real tr = p->tau_rho, te = p->tau_e, tee = p->tau_eps, tj = p->tau_j;
+    real taus[9] = {tr, te, tee, tj, tq, tj, tq, ts, ts};
+    for (int k = 0; k < 9; ++k) o->s[k] = 1.0L / taus[k];
+    if (invert_m(o->minv) != 0) { ora_destroy(o); return ORA_E_STATE; }
+    ora_init_rest(o);
+    *out = o;
+    return ORA_OK;
+}
+
+/* Boundary value for the unknown population i = ibar-bar at x_f, Eq. (EqNewBDSC) or (EqDBB). */
+static real boundary_value(const ora_ctx *o, int64_t k, int i, const real *fpre, const real *fpo, real rho,
+                           real ux, real uy)
+{
+    const real cs2 = 1.0L / 3.0L;
+    int ib = OPP[i];
+    real r = o->lr[k], l = o->ll[k], g = o->lg[k];
+    real ubx = o->lubx[k], uby = o->luby[k];
+    real cub = CX[i] * ubx + CY[i] * uby;
+    real udx = (o->p.diffuse == DIFFUSE_WALL) ? ubx : ux;
+    real udy = (o->p.diffuse == DIFFUSE_WALL) ? uby : uy;
+    real diffuse = (1.0L - r) * feq(i, rho, udx, udy);
+    if (o->p.bc_kind == BC_DBB)
+        return r * (fpo[ib] + 2.0L * weight(i) * rho * cub / cs2) + diffuse;
+    return r * ((1.0L + l - 2.0L * g) / (1.0L + l) * fpre[ib] + l / (1.0L + l) * fpo[i]
+                + (2.0L * g - l) / (1.0L + l) * fpo[ib] + 2.0L / (1.0L + l) * weight(i) * rho * cub / cs2)
+           + diffuse;
+}
+
+int ora_step(ora_ctx *o, int64_t nsteps)
+{
+    for (int64_t it = 0; it < nsteps; ++it) {
+        /* collision at every fluid node */
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < o->n; ++s) {
+            if (o->solid[s]) continue;
+            real rho, ux, uy;
+            collide(o, &o->f[s * 9], &o->fpost[s * 9], &rho, &ux, &uy);
+            o->ux_prev[s] = ux;
+            o->uy_prev[s] = uy;
+        }
+        /* streaming, with the boundary scheme for populations whose upstream node is solid */
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < o->n; ++s) {
+            if (o->solid[s]) continue;
+            int x = (int)(s % o->nx), y = (int)(s / o->nx);
+            real rho = 0.0L, ux = 0.0L, uy = 0.0L;
+            int have_macro = 0;
+            for (int i = 0; i < 9; ++i) {
+                int64_t src = neighbour(o, x, y, -CX[i], -CY[i]);
+                if (i == 0 || !o->solid[src]) {
+                    o->fnew[s * 9 + i] = o->fpost[src * 9 + i];
+                    continue;
+                }
+                if (!have_macro) { macro(o, &o->f[s * 9], &rho, &ux, &uy); have_macro = 1; }
+                int64_t k = o->linkidx[s * 9 + OPP[i]];
+                o->fnew[s * 9 + i] = boundary_value(o, k, i, &o->f[s * 9], &o->fpost[s * 9], rho, ux, uy);
+            }
+        }
+        /* mass entering through the wall links during this step */
+        real flux = 0.0L;
+        for (int64_t s = 0; s < o->n; ++s) {
+            if (o->solid[s]) continue;
+            for (int d = 1; d < 9; ++d) {
+                if (o->linkidx[s * 9 + d] < 0) continue;
+                flux += o->fnew[s * 9 + OPP[d]] - o->fpost[s * 9 + d];
+            }
+        }
+        o->last_link_flux = flux;
+        real *t = o->f; o->f = o->fnew; o->fnew = t;
+        o->steps_since_init++;
+    }
+    return ORA_OK;
+}
+
+/* rho and the half-force velocity at every site (0 on solid sites). */
+int ora_moments(const ora_ctx *o, double *rho, double *ux, double *uy)
+{
+    for (int64_t s = 0; s < o->n; ++s) {
+        if (o->solid[s]) { rho[s] = ux[s] = uy[s] = 0.0; continue; }
+        real r, a, b;
+        macro(o, &o->f[s * 9], &r, &a, &b);
+        rho[s] = (double)r; ux[s] = (double)a; uy[s] = (double)b;
+    }
+    return ORA_OK;
+}
+
+/* Residual R = sqrt(sum |u^n - u^(n-1)|^2 / sum |u^n|^2) over fluid nodes and the mass sum rho;
+ * R is +inf before the first step after an initialisation. */
+int ora_residual(const ora_ctx *o, double *residual, double *mass)
+{
+    real num = 0.0L, den = 0.0L, m = 0.0L;
+    for (int64_t s = 0; s < o->n; ++s) {
+        if (o->solid[s]) continue;
+        real r, a, b;
+        macro(o, &o->f[s * 9], &r, &a, &b);
+        m += r;
+        real dx = a - o->ux_prev[s], dy = b - o->uy_prev[s];
+        num += dx * dx + dy * dy;
+        den += a * a + b * b;
+    }
+    *mass = (double)m;
+    if (o->steps_since_init == 0) *residual = INFINITY;
+    else *residual = (double)sqrtl(num / den);
+    return ORA_OK;
+}
+
+/* Mass that entered through the wall links during the last step: sum over links of
+ * (f_i(x_f, t+1) - f'_ibar(x_f, t)). */
+double ora_last_link_flux(const ora_ctx *o) { return (double)o->last_link_flux; }
+
+/* Full population state (n * 9, site-major) in double. */
+int ora_get_f(const ora_ctx *o, double *out)
+{
+    for (int64_t s = 0; s < 9 * o->n; ++s) out[s] = (double)o->f[s];
+    return ORA_OK;
+}
+
+int ora_set_f(ora_ctx *o, const double *in)
+{
+    for (int64_t s = 0; s < 9 * o->n; ++s) o->f[s] = in[s];
+    o->steps_since_init = 0;
+    return ORA_OK;
+}
+
+/* M^-1 as computed (row-major 9x9), for the pin M M^-1 = I. */
+int ora_minv(double *out)
+{
+    real mi[9][9];
+    if (invert_m(mi) != 0) return ORA_E_STATE;
+    for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 9; ++j) out[i * 9 + j] = (double)mi[i][j];
+    return ORA_OK;
+}
+
+int64_t ora_steps(const ora_ctx *o) { return o->steps_since_init; }
+int ora_sizeof_params(void) { return (int)sizeof(ora_params); }
+int ora_sizeof_real(void) { return (int)sizeof(real); }
