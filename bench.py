@@ -1,0 +1,176 @@
+"""Throughput of the D2Q9 MRT + curved slip boundary step on one MI355X.
+
+Workload (throughput configuration): 4096 x 4096 doubly periodic lattice of random non-overlapping
+circular cylinders (porosity 0.7, radii U[8, 24] lattice units, seed 0), Kn = 0.05 with H = 32,
+body acceleration 1e-6, rest start, the paper's prescription for l, r and tau_q.
+
+One timed step is one pass of the hot path: the fused collide-stream-boundary kernel over the whole
+lattice, with the convergence monitor (residual and mass reductions) run every 100 steps as a
+steady-state solve would.  Inputs are resident in HBM before the timed region.  The headline value
+is FP32-shifted storage (fp32 deviations, fp32 collision); the FP64 storage figure is reported
+beside it.  MLUPS counts lattice sites (solid included); MFLUPS counts fluid nodes.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "D2Q9 MRT+curved-BC MLUPS & %HBM roofline; time-to-steady-state vs plain"
+HBM_PEAK_GBS = 8000.0
+CHECK_EVERY = 100
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_precision(problem, precision, steps, warmup, block, remap):
+    import torch
+    from paper_2012_14707_amd import lbm
+
+    lat = lbm.Lattice(problem, precision=precision)
+    lat.set_launch(block, remap)
+    info = lat.info
+    lat.step(warmup)
+    lat.residual()
+    lat.set_timing(True)
+    kernel_ms = 0.0
+    kernel_steps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(CHECK_EVERY, steps - done)
+        lat.step(k)
+        res, mass = lat.residual()   # synchronises
+        ms, n = lat.last_step_ms()
+        kernel_ms += ms
+        kernel_steps += n
+        done += k
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.set_timing(False)
+    ms_per_step = wall / steps * 1e3
+    kernel_avg_ms = kernel_ms / kernel_steps
+    out = dict(
+        ms_per_step=ms_per_step,
+        mlups=info["n_sites"] / (ms_per_step * 1e3),
+        mflups=info["n_fluid"] / (ms_per_step * 1e3),
+        kernel_avg_ms=kernel_avg_ms,
+        bytes_per_step=info["bytes_per_step"],
+        achieved_gbs=info["bytes_per_step"] / (kernel_avg_ms * 1e-3) / 1e9,
+        residual=res,
+        mass=mass,
+        n_sites=info["n_sites"],
+        n_fluid=info["n_fluid"],
+        n_links=info["n_links"],
+        n_clamped=info["n_clamped"],
+        tau_s=info["tau_s"],
+        tau_q=info["tau_q"],
+    )
+    lat.close()
+    return out
+
+
+def cpu_baseline(problem, steps=2):
+    """The oracle as it stands on this host's cores: `steps` steps of the full lattice."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ora = oracle.Oracle(problem["params"], problem["solid"], problem["links"])
+    t1 = time.perf_counter()
+    ora.step(steps)
+    t2 = time.perf_counter()
+    n_sites = problem["solid"].size
+    del ora
+    return dict(value=n_sites * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{steps} full steps of the 4096x4096 lattice (x87 extended precision, OpenMP over sites); "
+                       f"setup {t1 - t0:.1f} s excluded")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--remap", type=int, default=0)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
+              "the lattice would shard by rows with a halo exchange, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_14707_amd import geometry as G
+
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {args.n}x{args.n} random-cylinder lattice (seed 0)")
+    t0 = time.perf_counter()
+    pb = G.throughput_config3(n=args.n, seed=0)
+    log(f"[bench] geometry {time.perf_counter() - t0:.1f} s: {G.counts(pb)} (fluid, sites, links)")
+
+    results = {}
+    for precision in ([args.only] if args.only else ["fp32", "fp64"]):
+        log(f"[bench] {precision}: warmup {args.warmup}, timing {args.steps} steps")
+        results[precision] = time_precision(pb, precision, args.steps, args.warmup, args.block, args.remap)
+        r = results[precision]
+        log(f"[bench] {precision}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, kernel "
+            f"{r['kernel_avg_ms']:.4f} ms, {r['achieved_gbs']:.0f} GB/s algorithmic")
+
+    head = results.get("fp32") or results["fp64"]
+    head_name = "fp32" if "fp32" in results else "fp64"
+    line = {
+        "metric": METRIC,
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head_name == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"random circular cylinders {args.n}x{args.n}, porosity 0.7, R~U[8,24] lu, seed 0, "
+                        "periodic x/y, Kn=0.05 (H=32), a=1e-6, "
+                        + ("FP32-shifted populations" if head_name == "fp32" else "FP64 populations"),
+            "n_sites": head["n_sites"], "n_fluid": head["n_fluid"], "n_links": head["n_links"],
+            "residual_check_every": CHECK_EVERY, "block": args.block, "xcd_remap": bool(args.remap),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(head["achieved_gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "mflups": round(head["mflups"], 1),
+    }
+    if "fp64" in results and head_name != "fp64":
+        r = results["fp64"]
+        line["fp64"] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                        "mflups": round(r["mflups"], 1), "achieved_gbs": round(r["achieved_gbs"], 1),
+                        "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle, 2 steps of the full lattice on the host cores")
+        line["cpu_baseline"] = cpu_baseline(pb)
+        log(f"[bench] cpu baseline {line['cpu_baseline']['value']:.2f} MLUPS on {line['cpu_baseline']['cores']} threads")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

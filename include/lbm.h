@@ -1,0 +1,192 @@
+/*
+ * liblbm: MI355X (gfx950) D2Q9 multiple-relaxation-time lattice Boltzmann step with the local
+ * curved slip boundary of Wang, Tao, Hu, Zhang and Lu, "Curved boundary conditions of the
+ * lattice Boltzmann method for simulating microgaseous flows in the slip regime"
+ * (arXiv:2012.14707).
+ *
+ * Plain C ABI: every call returns an lbm_status; nothing throws across it.  The message of the
+ * last failure on the calling thread is available from lbm_last_error().
+ *
+ * Lattice units throughout: delta_x = delta_t = 1, c = 1, c_s^2 = 1/3.  Directions follow
+ * Eq. (Eq3): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.  Sites are row-major,
+ * site = y * nx + x.
+ *
+ * Memory: a context owns every device buffer it allocates.  Inputs passed to lbm_create are
+ * copied, so the caller may free them when it returns.  Outputs go to caller-owned buffers,
+ * either host memory or device memory (flag device_ptrs), sized as documented per call.
+ * A context is bound to the HIP device that was current at lbm_create and to one HIP stream;
+ * all device work is queued on that stream.  A context is not thread-safe; distinct contexts
+ * are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_E_INVAL (-1)    /* bad argument (null pointer, size, enum value) */
+#define LBM_E_NOMEM (-2)    /* device or host allocation failed */
+#define LBM_E_HIP (-3)      /* a HIP runtime call failed */
+#define LBM_E_GEOMETRY (-4) /* mask / wall-link table inconsistent */
+#define LBM_E_PARAM (-5)    /* physical parameters out of range (tau <= 1/2, 1 + l <= 0, r outside [0, 1]) */
+#define LBM_E_UNSTABLE (-6) /* the state went non-finite */
+#define LBM_E_STATE (-7)    /* call not valid in the context's current state */
+
+/* Free parameter l of Eq. (EqNewBDSC). */
+enum {
+    LBM_L_PAPER = 0,             /* Eq. (Eqexlva); l := 0 where it gives l < -0.4 (end of Sec. III.B) */
+    LBM_L_CLAMP_NEG = 1,         /* Eq. (Eqexlva); l := 0 where it gives l < 0 (stability fallback) */
+    LBM_L_ZERO = 2,              /* l = 0 (the "previous scheme" of Sec. III.B) */
+    LBM_L_GAMMA = 3,             /* l = gamma (Sec. IV comparisons) */
+    LBM_L_TWO_GAMMA = 4,         /* l = 2 gamma */
+    LBM_L_GAMMA2 = 5,            /* l = gamma^2 */
+    LBM_L_GAMMA2_PLUS_GAMMA = 6, /* l = gamma^2 + gamma */
+    LBM_L_FIXED = 7              /* l = l_override on every link */
+};
+/* Combination parameter r of Eq. (EqNewBDSC). */
+enum {
+    LBM_R_FROM_LEFF = 0, /* Eq. (SliCoeffrtsr) at the l actually used; equals Eq. (NSliCoertsr) where l is not clamped */
+    LBM_R_PAPER = 1,     /* Eq. (NSliCoertsr) as printed, also on clamped links */
+    LBM_R_FIXED = 2      /* r = r_override on every link */
+};
+/* Velocity of the Maxwell-diffuse equilibrium f_i^eq(rho_f, .) in Eq. (EqNewBDSC). */
+enum {
+    LBM_DIFFUSE_NODE = 0, /* u(x_f, t), the boundary node's half-force velocity: the reading under
+                             which the analysis of Sec. III.B (Eqs. (NumerSana)-(CoeC)) holds */
+    LBM_DIFFUSE_WALL = 1  /* u_b, the wall velocity (literal text of Sec. III.A) */
+};
+/* Population storage. */
+enum {
+    LBM_FP64 = 0,         /* fp64 deviations g_i = f_i - w_i rho0, fp64 collision */
+    LBM_FP32_SHIFTED = 1  /* fp32 deviations, fp32 collision; fp64 precompute and reductions */
+};
+
+/* One wall link: the fluid node x_f = (x, y), dir = the D2Q9 direction from x_f toward the solid
+ * node x_r (the paper's ibar, Fig. 1), q = gamma = |x_b - x_f| / |x_r - x_f| in (0, 1], and the
+ * wall velocity (ubx, uby) at the crossing point x_b. */
+typedef struct {
+    int32_t x, y, dir, reserved;
+    double q, ubx, uby;
+} lbm_link;
+
+/* Problem statement.  NaN in L1, L2 or E and values <= 0 in the *_override fields select the
+ * paper's prescription. */
+typedef struct {
+    int32_t nx, ny;                 /* lattice size (sites) */
+    int32_t periodic_x, periodic_y; /* 1 = periodic; otherwise the mask must pad that edge with solid */
+    double kn, h;                   /* Knudsen number and characteristic length H (lattice units):
+                                       tau_s = 1/2 + sqrt(6/pi) Kn H, Eq. (tKnrela) */
+    double sigma, L1, L2;           /* slip coefficients of Eq. (PhyscSlip); NaN L1/L2 -> Sec. IV model
+                                       L1 = (2 - sigma)(1 - 0.1817 sigma)/sigma, L2 = 1/pi + L1^2/2 */
+    double E;                       /* constant of Eq. (Eqexlva); NaN -> min(-0.65, E_max - 0.05) with
+                                       E_max the bound of Eq. (EqECond) */
+    double tau_rho, tau_e, tau_eps, tau_j; /* non-hydrodynamic relaxation times (Sec. IV: 1.0, 1.1, 1.2, 1.0) */
+    double tau_s_override, tau_q_override; /* > 0: use instead of Eqs. (tKnrela) / (NSliCoertstq) */
+    double r_override, l_override;         /* used by LBM_R_FIXED / LBM_L_FIXED */
+    int32_t l_mode, r_mode, diffuse, precision;
+    double ax, ay;                  /* body acceleration a; the force density is rho a (Sec. III.B) */
+    double rho0;                    /* reference density of the rest state (1) */
+} lbm_params;
+
+typedef struct {
+    double tau_s, tau_q, E, E_max, L1, L2, nu; /* derived parameters; nu = (tau_s - 1/2)/3, Eq. (EqViscos) */
+    int64_t n_sites, n_fluid, n_links;
+    int32_t n_clamped;    /* links where the l mode reset l */
+    int32_t n_nonconvex;  /* links with l outside [max(0, 2 gamma - 1), 2 gamma] (Sec. III.A) */
+    int32_t precision;
+    int32_t reserved;
+    int64_t bytes_per_step; /* algorithmic HBM bytes of one step: 18 s per fluid node + 5 s per link
+                               + 1 flag byte per site + 4 bytes per 64-site chunk (s = 8 or 4) */
+    int64_t steps;          /* steps taken since the last initialisation */
+} lbm_info;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t lbm_version(void);
+
+/* Message of the last failing call on this thread ("" if none).  Owned by the library. */
+const char *lbm_last_error(void);
+
+/* Fills *p with the paper's defaults: sigma = 1, L1/L2/E = NaN (derived), tau_rho = tau_j = 1,
+ * tau_e = 1.1, tau_eps = 1.2 (Sec. IV), no overrides, LBM_L_PAPER, LBM_R_FROM_LEFF,
+ * LBM_DIFFUSE_NODE, LBM_FP64, a = 0, rho0 = 1, non-periodic. */
+lbm_status lbm_params_default(lbm_params *p);
+
+/* Creates a lattice (Sec. III.A problem statement).
+ *   solid    host, uint8 [ny * nx] row-major, nonzero = solid (closed set: nodes on a wall are solid)
+ *   links    host, n_links records; every (fluid node, direction) whose neighbour is solid must
+ *            appear exactly once; order is free
+ *   stream   hipStream_t for all device work of this context (NULL = the null stream)
+ * Validation (LBM_E_GEOMETRY): x_f fluid and x_f + c_dir solid, 0 < q <= 1, finite wall velocity,
+ * no duplicate, no missing link, no fluid node on a non-periodic edge, no fluid node whose eight
+ * neighbours are all solid.  LBM_E_PARAM: tau_s or tau_q <= 1/2, any tau <= 1/2, 1 + l <= 0 or
+ * r outside [0, 1] on some link.  On success *out owns the device state, initialised to rest
+ * (f_i = w_i rho0).  On failure *out is NULL and nothing is leaked. */
+lbm_status lbm_create(const lbm_params *p, const uint8_t *solid, const lbm_link *links, int64_t n_links,
+                      void *stream, lbm_ctx **out);
+
+/* Releases every device and host resource of ctx (NULL is accepted). Synchronises the stream. */
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+lbm_status lbm_get_info(const lbm_ctx *ctx, lbm_info *info);
+
+/* Per-link boundary coefficients as computed on the device in fp64, in the caller's link order:
+ * out (host) [n_links * 8] = (l_raw, l_eff, r, alpha1, alpha2, alpha3, beta, kappa) per link, where
+ * Eq. (EqNewBDSC) reads f_i(x_f, t+1) = alpha1 f_ibar(x_f,t) + alpha2 f'_i(x_f,t) + alpha3 f'_ibar(x_f,t)
+ * + beta rho_f + kappa f_i^eq(rho_f, u_d):  alpha1 = r(1+l-2 gamma)/(1+l), alpha2 = r l/(1+l),
+ * alpha3 = r(2 gamma - l)/(1+l), beta = 2 r/(1+l) w_i c_i.u_b / c_s^2 (+ kappa w_i phi_i(u_b) under
+ * LBM_DIFFUSE_WALL, where the wall equilibrium is folded into beta), kappa = 1 - r. */
+lbm_status lbm_link_coeffs(lbm_ctx *ctx, double *out);
+
+/* Rest state f_i = w_i rho0 everywhere. */
+lbm_status lbm_init_rest(lbm_ctx *ctx);
+
+/* State f_i = f_i^eq(rho, u - a/2) at fluid nodes, so that the half-force velocity of
+ * Eq. (FluidMacr) equals u.  rho, ux, uy: fp64 [ny * nx], host (device_ptrs = 0) or device
+ * (device_ptrs = 1); values on solid sites are ignored.  Non-finite input is accepted and is
+ * reported by the next lbm_residual as LBM_E_UNSTABLE. */
+lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy, int32_t device_ptrs);
+
+/* Advances nsteps >= 0 time steps: per fluid node, collision in moment space (Eqs. (LBEColli),
+ * (LBEforce), (MomentPost)) fused with streaming, and for each wall link the boundary value of
+ * Eq. (EqNewBDSC).  Asynchronous on the context's stream. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* rho and the half-force velocity u (Eq. (FluidMacr)) at every site, 0 on solid sites.
+ * rho, ux, uy: fp64 [ny * nx], host or device.  Synchronises the stream for host outputs. */
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy, int32_t device_ptrs);
+
+/* Convergence residual and mass, fp64 reductions over fluid nodes in a fixed order:
+ *   residual = sqrt(sum |u(t) - u(t-1)|^2 / sum |u(t)|^2), +inf if no step since initialisation,
+ *   mass = sum rho.
+ * Synchronises the stream.  Returns LBM_E_UNSTABLE (with the values still written) when either
+ * is not finite. */
+lbm_status lbm_residual(lbm_ctx *ctx, double *residual, double *mass);
+
+/* Re-binds the context to another stream of the same device (NULL = null stream). */
+lbm_status lbm_set_stream(lbm_ctx *ctx, void *stream);
+
+/* Waits for all work queued by this context. */
+lbm_status lbm_synchronize(lbm_ctx *ctx);
+
+/* Launch shape of the step kernel: block = threads per block (64..1024, multiple of 64),
+ * xcd_remap = 1 to map consecutive lattice chunks to one XCD.  Results do not depend on it. */
+lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block, int32_t xcd_remap);
+
+/* Average duration in milliseconds of the step kernel launches of the last lbm_step call,
+ * measured with HIP events on the context's stream (0 if timing is off).  Timing is switched on
+ * by lbm_set_timing(ctx, 1); it records one event pair per lbm_step call. */
+lbm_status lbm_set_timing(lbm_ctx *ctx, int32_t on);
+lbm_status lbm_last_step_ms(lbm_ctx *ctx, double *ms_total, int64_t *nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,254 @@
+"""ctypes binding of liblbm (include/lbm.h): argument marshalling only.
+
+Every step of the lattice path runs in the HIP kernels of ``lib/liblbm.so``; this module turns a
+problem dict (``paper_2012_14707_amd.geometry``) into the C structs, passes torch device
+pointers and the current torch stream, and raises ``LbmError`` on any non-zero status.  It
+fails loudly when the library is missing: there is no CPU fallback.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "liblbm.so")
+
+L_MODES = {"paper": 0, "clamp_neg": 1, "zero": 2, "gamma": 3, "two_gamma": 4, "gamma2": 5,
+           "gamma2_plus_gamma": 6, "fixed": 7}
+R_MODES = {"from_leff": 0, "paper": 1, "fixed": 2}
+DIFFUSE = {"node": 0, "wall": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_GEOMETRY",
+          -5: "LBM_E_PARAM", -6: "LBM_E_UNSTABLE", -7: "LBM_E_STATE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Link(C.Structure):
+    _fields_ = [("x", C.c_int32), ("y", C.c_int32), ("dir", C.c_int32), ("reserved", C.c_int32),
+                ("q", C.c_double), ("ubx", C.c_double), ("uby", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+        ("kn", C.c_double), ("h", C.c_double), ("sigma", C.c_double), ("L1", C.c_double), ("L2", C.c_double),
+        ("E", C.c_double), ("tau_rho", C.c_double), ("tau_e", C.c_double), ("tau_eps", C.c_double),
+        ("tau_j", C.c_double), ("tau_s_override", C.c_double), ("tau_q_override", C.c_double),
+        ("r_override", C.c_double), ("l_override", C.c_double),
+        ("l_mode", C.c_int32), ("r_mode", C.c_int32), ("diffuse", C.c_int32), ("precision", C.c_int32),
+        ("ax", C.c_double), ("ay", C.c_double), ("rho0", C.c_double),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [("tau_s", C.c_double), ("tau_q", C.c_double), ("E", C.c_double), ("E_max", C.c_double),
+                ("L1", C.c_double), ("L2", C.c_double), ("nu", C.c_double),
+                ("n_sites", C.c_int64), ("n_fluid", C.c_int64), ("n_links", C.c_int64),
+                ("n_clamped", C.c_int32), ("n_nonconvex", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32), ("bytes_per_step", C.c_int64), ("steps", C.c_int64)]
+
+
+# Every entry point of include/lbm.h with its ctypes signature.
+_VP = C.c_void_p
+_DPTR = C.POINTER(C.c_double)
+SIGNATURES = {
+    "lbm_version": (C.c_int32, []),
+    "lbm_last_error": (C.c_char_p, []),
+    "lbm_params_default": (C.c_int32, [C.POINTER(Params)]),
+    "lbm_create": (C.c_int32, [C.POINTER(Params), _VP, C.POINTER(Link), C.c_int64, _VP, C.POINTER(_VP)]),
+    "lbm_destroy": (C.c_int32, [_VP]),
+    "lbm_get_info": (C.c_int32, [_VP, C.POINTER(Info)]),
+    "lbm_link_coeffs": (C.c_int32, [_VP, _VP]),
+    "lbm_init_rest": (C.c_int32, [_VP]),
+    "lbm_init_fields": (C.c_int32, [_VP, _VP, _VP, _VP, C.c_int32]),
+    "lbm_step": (C.c_int32, [_VP, C.c_int64]),
+    "lbm_moments": (C.c_int32, [_VP, _VP, _VP, _VP, C.c_int32]),
+    "lbm_residual": (C.c_int32, [_VP, _DPTR, _DPTR]),
+    "lbm_set_stream": (C.c_int32, [_VP, _VP]),
+    "lbm_synchronize": (C.c_int32, [_VP]),
+    "lbm_set_launch": (C.c_int32, [_VP, C.c_int32, C.c_int32]),
+    "lbm_set_timing": (C.c_int32, [_VP, C.c_int32]),
+    "lbm_last_step_ms": (C.c_int32, [_VP, _DPTR, C.POINTER(C.c_int64)]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads liblbm.so (after torch, so that both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2012_14707_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback")
+    import torch  # noqa: F401  (loads torch's HIP runtime first; liblbm then binds to the same one)
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        raise LbmError(status, _lib.lbm_last_error().decode())
+
+
+def make_params(params, shape, precision="fp64"):
+    """C parameter struct from a problem's physical inputs (names as in geometry.base_params)."""
+    lib = load()
+    p = Params()
+    _check(lib.lbm_params_default(C.byref(p)))
+    ny, nx = shape
+    p.nx, p.ny = nx, ny
+    for name, _ in Params._fields_:
+        if name in ("nx", "ny", "precision"):
+            continue
+        if name in params:
+            v = params[name]
+            if name == "l_mode":
+                v = L_MODES[v]
+            elif name == "r_mode":
+                v = R_MODES[v]
+            elif name == "diffuse":
+                v = DIFFUSE[v]
+            setattr(p, name, v)
+    p.precision = PRECISION[precision]
+    return p
+
+
+def make_links(links):
+    n = len(links["x"])
+    arr = (Link * max(n, 1))()
+    if n:
+        a = np.frombuffer(arr, dtype=np.dtype([("x", "<i4"), ("y", "<i4"), ("dir", "<i4"), ("reserved", "<i4"),
+                                               ("q", "<f8"), ("ubx", "<f8"), ("uby", "<f8")]), count=n)
+        a["x"] = links["x"]
+        a["y"] = links["y"]
+        a["dir"] = links["dir"]
+        a["q"] = links["q"]
+        a["ubx"] = links["ubx"]
+        a["uby"] = links["uby"]
+    return arr, n
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Lattice:
+    """One lattice context of liblbm on the current torch device and stream."""
+
+    def __init__(self, problem, precision="fp64", stream=None):
+        lib = load()
+        self._lib = lib
+        solid = np.ascontiguousarray(problem["solid"], dtype=np.uint8)
+        self.shape = solid.shape
+        self.precision = precision
+        p = make_params(problem["params"], solid.shape, precision)
+        links, n = make_links(problem["links"])
+        h = C.c_void_p()
+        _check(lib.lbm_create(C.byref(p), solid.ctypes.data_as(C.c_void_p), links, n, _stream_handle(stream),
+                              C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        i = Info()
+        _check(self._lib.lbm_get_info(self._h, C.byref(i)))
+        return {name: getattr(i, name) for name, _ in Info._fields_}
+
+    def link_coeffs(self):
+        """[n_links, 8]: l_raw, l_eff, r, alpha1, alpha2, alpha3, beta, kappa (caller's link order)."""
+        n = self.info["n_links"]
+        out = np.zeros((max(n, 1), 8))
+        _check(self._lib.lbm_link_coeffs(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out[:n]
+
+    def init_rest(self):
+        _check(self._lib.lbm_init_rest(self._h))
+
+    def init_fields(self, rho, ux, uy):
+        """rho, ux, uy: torch float64 CUDA tensors or numpy float64 arrays of the lattice shape."""
+        import torch
+        if isinstance(rho, torch.Tensor):
+            t = [x.contiguous() for x in (rho, ux, uy)]
+            for x in t:
+                if x.dtype != torch.float64 or not x.is_cuda or tuple(x.shape) != self.shape:
+                    raise ValueError("fields must be float64 CUDA tensors of the lattice shape")
+            _check(self._lib.lbm_init_fields(self._h, *[C.c_void_p(x.data_ptr()) for x in t], 1))
+        else:
+            a = [np.ascontiguousarray(x, dtype=np.float64).reshape(self.shape) for x in (rho, ux, uy)]
+            _check(self._lib.lbm_init_fields(self._h, *[x.ctypes.data_as(C.c_void_p) for x in a], 0))
+
+    def step(self, n=1):
+        _check(self._lib.lbm_step(self._h, int(n)))
+
+    def moments(self, out=None):
+        """(rho, ux, uy) as float64 CUDA tensors (written on the current stream)."""
+        import torch
+        if out is None:
+            out = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        _check(self._lib.lbm_moments(self._h, *[C.c_void_p(x.data_ptr()) for x in out], 1))
+        return out
+
+    def moments_host(self):
+        a = [np.zeros(self.shape) for _ in range(3)]
+        _check(self._lib.lbm_moments(self._h, *[x.ctypes.data_as(C.c_void_p) for x in a], 0))
+        return a
+
+    def residual(self, raise_unstable=True):
+        r, m = C.c_double(), C.c_double()
+        st = self._lib.lbm_residual(self._h, C.byref(r), C.byref(m))
+        if st != 0 and (raise_unstable or st != -6):
+            _check(st)
+        return r.value, m.value
+
+    def synchronize(self):
+        _check(self._lib.lbm_synchronize(self._h))
+
+    def set_launch(self, block=256, xcd_remap=False):
+        _check(self._lib.lbm_set_launch(self._h, int(block), int(bool(xcd_remap))))
+
+    def set_timing(self, on=True):
+        _check(self._lib.lbm_set_timing(self._h, int(bool(on))))
+
+    def last_step_ms(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(self._lib.lbm_last_step_ms(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def run_to_steady(self, tol, check_every=100, max_steps=2_000_000):
+        res = math.inf
+        steps = 0
+        while steps < max_steps:
+            self.step(check_every)
+            steps += check_every
+            res, _ = self.residual()
+            if res <= tol:
+                break
+        return steps, res

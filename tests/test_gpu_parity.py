@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, element by element.
+
+Bar (BASELINE the benchmark spec): FP64 storage within 1e-12 and FP32-shifted storage within 1e-5 of the
+oracle, as relative max velocity error max_x |u_gpu - u_ora| / max_x |u_ora| over fluid nodes at
+equal step counts.  Integer work (link ordering, flags, chunk offsets) is covered through these
+comparisons: a misplaced link coefficient changes the velocity at O(1) relative level.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_14707_amd import geometry as G
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2012_14707_amd import lbm
+    lbm.load()
+    yield
+
+
+def _lattice(problem, precision="fp64", **over):
+    from paper_2012_14707_amd import lbm
+    pb = dict(problem)
+    pb["params"] = dict(problem["params"], **over)
+    return lbm.Lattice(pb, precision=precision)
+
+
+def _oracle(problem, **over):
+    return oracle.Oracle(dict(problem["params"], **over), problem["solid"], problem["links"])
+
+
+def rel_err(gpu, ora, solid):
+    fl = solid == 0
+    _, ug, vg = gpu
+    _, uo, vo = ora
+    num = np.max(np.hypot(ug - uo, vg - vo)[fl])
+    den = np.max(np.hypot(uo, vo)[fl])
+    return num / den
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare(problem, steps, precision="fp64", tol=None, init=None, **over):
+    _say(f"[parity] {problem['meta']['kind']} {problem['solid'].shape} {precision} steps={steps} {over}")
+    lat = _lattice(problem, precision, **over)
+    ora = _oracle(problem, **over)
+    if init is not None:
+        lat.init_fields(*init)
+        ora.init_fields(*init)
+    lat.step(steps)
+    ora.step(steps)
+    g = lat.moments_host()
+    o = ora.moments()
+    err = rel_err(g, o, problem["solid"])
+    rg, mg = lat.residual()
+    ro, mo = ora.residual()
+    _say(f"    rel velocity error {err:.3e}  mass {mg:.15e} vs {mo:.15e}  residual {rg:.3e} vs {ro:.3e}")
+    assert err <= (tol or TOL[precision]), err
+    assert abs(mg - mo) / mo < (1e-12 if precision == "fp64" else 1e-6)
+    rho_err = np.max(np.abs(g[0] - o[0])[problem["solid"] == 0])
+    assert rho_err < (1e-13 if precision == "fp64" else 1e-6), rho_err
+    return lat, ora, err
+
+
+def test_config1_fp64_steady_parity():
+    """Config 1 run to residual 1e-10 on both sides with checks every 100 steps: same step count,
+    velocities within 1e-12, and the GPU field reproduces Eq. (numvelo) like the oracle does."""
+    pb = G.poiseuille_config1()
+    lat = _lattice(pb)
+    ora = _oracle(pb)
+    sg, rg = lat.run_to_steady(1e-10, 100, 100_000)
+    so, ro = ora.run_to_steady(1e-10, 100, 100_000)
+    assert sg == so
+    assert rg == pytest.approx(ro, rel=1e-3)
+    err = rel_err(lat.moments_host(), ora.moments(), pb["solid"])
+    _say(f"[config1] steps {sg} residual {rg:.3e}/{ro:.3e} rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("kn", [0.1, 0.05, 0.01])
+def test_couette_fp64_parity(kn):
+    compare(G.couette_config2(kn), 2000, "fp64", L1=1.0, L2=0.0)
+
+
+@functools.lru_cache(maxsize=None)
+def _couette_steady(kn):
+    pb = G.couette_config2(kn)
+    ora = _oracle(pb, L1=1.0, L2=0.0)
+    steps, res = ora.run_to_steady(1e-10, 200, 60_000)
+    return steps, ora.moments()
+
+
+@pytest.mark.parametrize("kn", [0.1, 0.05, 0.01])
+def test_couette_fp32_steady_parity(kn):
+    """FP32-shifted storage against the fp64-converged oracle at the oracle's step count (config 2)."""
+    pb = G.couette_config2(kn)
+    steps, o = _couette_steady(kn)
+    lat = _lattice(pb, "fp32", L1=1.0, L2=0.0)
+    lat.step(steps)
+    err = rel_err(lat.moments_host(), o, pb["solid"])
+    res, _ = lat.residual()
+    _say(f"[couette fp32] Kn={kn} steps={steps} rel err {err:.3e} fp32 residual {res:.2e}")
+    assert err <= 1e-5
+
+
+def test_couette_fp64_steady_parity():
+    pb = G.couette_config2(0.05)
+    steps, o = _couette_steady(0.05)
+    lat = _lattice(pb, "fp64", L1=1.0, L2=0.0)
+    lat.step(steps)
+    err = rel_err(lat.moments_host(), o, pb["solid"])
+    _say(f"[couette fp64 steady] steps={steps} rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+@functools.lru_cache(maxsize=None)
+def _cylinders(n, seed):
+    return G.random_cylinders(n=n, porosity=0.7, rmin=8, rmax=24, seed=seed, kn=0.05, h=32.0, ax=1e-6)
+
+
+def _smooth_fields(shape, seed, amp=1e-3):
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    y, x = np.mgrid[0:ny, 0:nx]
+    kx, ky = rng.integers(1, 4, 2)
+    ph = rng.random(3) * 2 * np.pi
+    rho = 1.0 + 0.01 * np.sin(2 * np.pi * kx * x / nx + ph[0])
+    ux = amp * np.cos(2 * np.pi * ky * y / ny + ph[1])
+    uy = 0.5 * amp * np.sin(2 * np.pi * kx * x / nx + ph[2])
+    return rho, ux, uy
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cylinder_patch_parity(precision):
+    """256^2 doubly periodic random cylinders (several tiles, every link direction, clamped links),
+    from smooth non-trivial fields so every term of the collision is exercised."""
+    pb = _cylinders(256, 11)
+    compare(pb, 300, precision, init=_smooth_fields(pb["solid"].shape, 5))
+
+
+@pytest.mark.parametrize("over", [
+    dict(l_mode="zero", r_mode="paper"),
+    dict(l_mode="gamma"),
+    dict(l_mode="two_gamma"),
+    dict(l_mode="gamma2"),
+    dict(l_mode="gamma2_plus_gamma"),
+    dict(l_mode="clamp_neg"),
+    dict(l_mode="fixed", l_override=0.3, r_mode="fixed", r_override=0.7),
+    dict(diffuse="wall"),
+    dict(diffuse="wall", l_mode="gamma"),
+])
+def test_mode_parity_annulus(over):
+    """Every l, r and diffuse mode on a small annulus with a moving inner wall."""
+    pb = G.annulus(40, 8.0, 18.0, (19.5, 19.5), u_inner=0.02, u_outer=-0.01, kn=0.05)
+    compare(pb, 400, "fp64", init=_smooth_fields(pb["solid"].shape, 2), **over)
+    compare(pb, 400, "fp32", **over)
+
+
+def test_dbb_remark2_on_gpu():
+    """Remark 2 through the GPU path: gamma = 1/2, l = 0 against the oracle's separately coded DBB."""
+    pb = G.channel(9, nx=3, gamma=0.5, kn=0.0, ax=1e-5, u_bottom=3e-3, tau_s_override=1.3, tau_q_override=0.9,
+                   r_mode="fixed", r_override=0.7, l_mode="zero")
+    lat = _lattice(pb)
+    ora = _oracle(pb, bc="dbb")
+    lat.step(500)
+    ora.step(500)
+    err = rel_err(lat.moments_host(), ora.moments(), pb["solid"])
+    assert err <= 1e-12
+
+
+def test_link_coefficient_parity():
+    """Per-link precompute (fp64 on the device) against the oracle's prescription and the
+    coefficients of Eq. (EqNewBDSC) written out on the test side."""
+    pb = G.couette_config2(0.01)
+    for over in (dict(), dict(r_mode="paper"), dict(l_mode="clamp_neg"), dict(diffuse="wall")):
+        lat = _lattice(pb, **over)
+        c = lat.link_coeffs()
+        _, lk = oracle.derive(dict(pb["params"], **over), pb["links"]["q"])
+        np.testing.assert_allclose(c[:, 0], lk[:, 0], rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(c[:, 1], lk[:, 1], rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(c[:, 2], lk[:, 2], rtol=1e-14, atol=1e-15)
+        g, l, r = pb["links"]["q"], lk[:, 1], lk[:, 2]
+        np.testing.assert_allclose(c[:, 3], r * (1 + l - 2 * g) / (1 + l), rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(c[:, 4], r * l / (1 + l), rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(c[:, 5], r * (2 * g - l) / (1 + l), rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(c[:, 7], 1 - r, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(c[:, 3] + c[:, 4] + c[:, 5], r, rtol=1e-14)
+        info = lat.info
+        assert info["n_clamped"] == int(np.sum(lk[:, 0] != lk[:, 1]))
+        assert info["n_links"] == len(g)
+
+
+def test_ragged_small_lattices():
+    """Sizes that are not multiples of the 64-site chunk, tiny and degenerate lattices."""
+    # 37 x 23, periodic in x, one off-centre cylinder plus channel walls
+    s = np.zeros((23, 37), np.uint8)
+    s[0], s[-1] = 1, 1
+    yy, xx = np.mgrid[0:23, 0:37]
+    s[(xx - 17.3) ** 2 + (yy - 11.6) ** 2 <= 4.2 ** 2] = 1
+    xs, ys, ds = G.wall_candidates(s, 1, 0)
+    rng = np.random.default_rng(0)
+    q = rng.uniform(0.05, 1.0, len(xs))
+    pb = dict(params=G.base_params(periodic_x=1, kn=0.05, h=21.0, ax=1e-5), solid=s,
+              links=dict(x=xs, y=ys, dir=ds, q=q, ubx=np.zeros(len(xs)), uby=np.zeros(len(xs))),
+              meta=dict(kind="ragged"))
+    compare(pb, 700, "fp64")
+    compare(pb, 700, "fp32")
+    # fully periodic box without walls or links, with force: 3 x 1 and 1 x 1
+    for shape in ((1, 3), (1, 1), (5, 2)):
+        pb = dict(params=G.base_params(periodic_x=1, periodic_y=1, tau_s_override=0.8, tau_q_override=1.1,
+                                       ax=1e-4, ay=-2e-5), solid=np.zeros(shape, np.uint8),
+                  links=G._empty_links(), meta=dict(kind="box"))
+        compare(pb, 50, "fp64", init=(np.full(shape, 1.02), np.full(shape, 1e-3), np.zeros(shape)))
+
+
+def test_config1_fp32_and_modes():
+    pb = G.poiseuille_config1()
+    compare(pb, 1100, "fp32")
+
+
+def test_residual_mass_and_nonfinite():
+    from paper_2012_14707_amd import lbm
+    pb = G.couette_config2(0.1)
+    lat = _lattice(pb)
+    r0, m0 = lat.residual()
+    assert math.isinf(r0)
+    assert m0 == pytest.approx(float((pb["solid"] == 0).sum()), rel=1e-15)
+    lat.step(10)
+    r1, _ = lat.residual()
+    assert math.isfinite(r1) and r1 > 0
+    # non-finite state is reported, not hidden
+    shape = pb["solid"].shape
+    rho = np.ones(shape)
+    rho[60, 30] = np.nan
+    lat.init_fields(rho, np.zeros(shape), np.zeros(shape))
+    lat.step(3)
+    with pytest.raises(lbm.LbmError) as e:
+        lat.residual()
+    assert e.value.status == -6
+
+
+def test_device_parameter_error():
+    from paper_2012_14707_amd import lbm
+    with pytest.raises(lbm.LbmError) as e:
+        _lattice(G.couette_config2(0.05), l_mode="fixed", l_override=-1.0)
+    assert e.value.status == -5
+
+
+def test_launch_shapes_bitwise():
+    """The launch shape (block size, XCD remap) does not change a single bit of the result."""
+    pb = _cylinders(256, 11)
+    ref = None
+    for precision in ("fp64", "fp32"):
+        ref = None
+        for block in (64, 128, 256, 512, 1024):
+            for remap in (False, True):
+                lat = _lattice(pb, precision)
+                lat.set_launch(block, remap)
+                lat.init_fields(*_smooth_fields(pb["solid"].shape, 5))
+                lat.step(37)
+                out = np.stack(lat.moments_host())
+                if ref is None:
+                    ref = out
+                assert np.array_equal(out, ref), (precision, block, remap)
+
+
+def test_device_pointer_paths():
+    import torch
+    pb = _cylinders(256, 11)
+    lat = _lattice(pb, "fp32")
+    f = [torch.tensor(a, device="cuda") for a in _smooth_fields(pb["solid"].shape, 3)]
+    lat.init_fields(*f)
+    lat.step(5)
+    d = [t.cpu().numpy() for t in lat.moments()]
+    torch.cuda.synchronize()
+    h = lat.moments_host()
+    for a, b in zip(d, h):
+        assert np.array_equal(a, b)
