@@ -31,12 +31,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_precision(problem, precision, steps, warmup, block, remap):
+def time_precision(problem, precision, steps, warmup, block):
     import torch
     from paper_2012_14707_amd import lbm
 
     lat = lbm.Lattice(problem, precision=precision)
-    lat.set_launch(block, remap)
+    lat.set_launch(block)
     info = lat.info
     lat.step(warmup)
     lat.residual()
@@ -101,10 +101,11 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--remap", type=int, default=0)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (20 times) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
@@ -115,6 +116,19 @@ def main():
     from paper_2012_14707_amd import geometry as G
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 20
+        print(json.dumps({"copy_mib": args.copy_calibration, "read_bytes": 4 * n, "write_bytes": 4 * n,
+                          "ms": dt * 1e3, "gbs_read_plus_write": 8 * n / dt / 1e9}), flush=True)
+        return
     log(f"[bench] generating {args.n}x{args.n} random-cylinder lattice (seed 0)")
     t0 = time.perf_counter()
     pb = G.throughput_config3(n=args.n, seed=0)
@@ -123,7 +137,7 @@ def main():
     results = {}
     for precision in ([args.only] if args.only else ["fp32", "fp64"]):
         log(f"[bench] {precision}: warmup {args.warmup}, timing {args.steps} steps")
-        results[precision] = time_precision(pb, precision, args.steps, args.warmup, args.block, args.remap)
+        results[precision] = time_precision(pb, precision, args.steps, args.warmup, args.block)
         r = results[precision]
         log(f"[bench] {precision}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, kernel "
             f"{r['kernel_avg_ms']:.4f} ms, {r['achieved_gbs']:.0f} GB/s algorithmic")
@@ -148,7 +162,7 @@ def main():
                         "periodic x/y, Kn=0.05 (H=32), a=1e-6, "
                         + ("FP32-shifted populations" if head_name == "fp32" else "FP64 populations"),
             "n_sites": head["n_sites"], "n_fluid": head["n_fluid"], "n_links": head["n_links"],
-            "residual_check_every": CHECK_EVERY, "block": args.block, "xcd_remap": bool(args.remap),
+            "residual_check_every": CHECK_EVERY, "block": args.block,
         },
         "roofline": {
             "bound": "hbm",

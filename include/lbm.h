@@ -175,9 +175,9 @@ lbm_status lbm_set_stream(lbm_ctx *ctx, void *stream);
 /* Waits for all work queued by this context. */
 lbm_status lbm_synchronize(lbm_ctx *ctx);
 
-/* Launch shape of the step kernel: block = threads per block (64..1024, multiple of 64),
- * xcd_remap = 1 to map consecutive lattice chunks to one XCD.  Results do not depend on it. */
-lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block, int32_t xcd_remap);
+/* Threads per block of the step kernel: 64, 128, 256 (default), 512 or 1024.  Results do not
+ * depend on it.  LBM_E_INVAL if the block's wall links would not fit the LDS staging area. */
+lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block);
 
 /* Average duration in milliseconds of the step kernel launches of the last lbm_step call,
  * measured with HIP events on the context's stream (0 if timing is off).  Timing is switched on

@@ -45,6 +45,9 @@ const int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 bool is_set(double v) { return std::isfinite(v) && v > 0.0; }
 
+// LDS a step-kernel block may use for its link staging area.
+constexpr size_t kMaxLds = 64 * 1024;
+
 }  // namespace
 
 struct lbm_ctx {
@@ -52,6 +55,7 @@ struct lbm_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     uint32_t nx = 0, ny = 0, n = 0;
+    uint32_t ps = 0;  // population plane stride: n rounded up to whole 64-site chunks
     int64_t n_fluid = 0, n_links = 0;
     double tau_s = 0, tau_q = 0, L1 = 0, L2 = 0, E = 0, E_max = 0;
     int32_t n_clamped = 0, n_nonconvex = 0;
@@ -60,8 +64,12 @@ struct lbm_ctx {
     int32_t* d_chunk = nullptr;
     double* d_coef64 = nullptr;  // 8 rows of n_links
     float* d_coef32 = nullptr;   // 5 rows of n_links (fp32 storage only)
-    void* d_buf[2] = {nullptr, nullptr};
+    void* d_buf[2] = {nullptr, nullptr};   // population planes, two time levels
+    void* d_link[2] = {nullptr, nullptr};  // per-link incoming populations, two time levels
     int cur = 0;
+    std::vector<int32_t> chunk;            // host copy of the chunk link offsets
+    uint32_t nchunks = 0;
+    uint32_t lds_links = 0;                // LDS link slots for the current block size
     double* d_uprev = nullptr;   // 2 n
     double* d_partial = nullptr;
     double* d_result = nullptr;  // 4
@@ -70,7 +78,6 @@ struct lbm_ctx {
     int64_t steps = 0;
     bool uprev_valid = false;
     int block = 256;
-    bool xcd_remap = false;
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_timing = false;
@@ -78,7 +85,20 @@ struct lbm_ctx {
     bool on_device = false;
 
     bool fp32() const { return p.precision == LBM_FP32_SHIFTED; }
-    size_t pop_bytes() const { return (fp32() ? 4 : 8) * size_t(9) * n; }
+    size_t pop_bytes() const { return (fp32() ? 4 : 8) * size_t(9) * ps; }
+    size_t link_bytes() const { return (fp32() ? 4 : 8) * size_t(n_links > 0 ? n_links : 1); }
+    lbm::Geo geo() const { return lbm::Geo{d_flags, d_chunk, n, nx, ny, nchunks, ps}; }
+    // Most wall links owned by one block of `blk` sites.
+    uint32_t max_links_per_block(int blk) const
+    {
+        const uint32_t per = uint32_t(blk) / lbm::kChunk;
+        uint32_t best = 0;
+        for (uint32_t c0 = 0; c0 < nchunks; c0 += per) {
+            const uint32_t c1 = std::min(c0 + per, nchunks);
+            best = std::max(best, uint32_t(chunk[c1] - chunk[c0]));
+        }
+        return best;
+    }
 };
 
 namespace {
@@ -98,7 +118,8 @@ void release(lbm_ctx* c)
     ignore(hipSetDevice(c->device));
     ignore(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     for (void* ptr : {static_cast<void*>(c->d_flags), static_cast<void*>(c->d_chunk), static_cast<void*>(c->d_coef64),
-                      static_cast<void*>(c->d_coef32), c->d_buf[0], c->d_buf[1], static_cast<void*>(c->d_uprev),
+                      static_cast<void*>(c->d_coef32), c->d_buf[0], c->d_buf[1], c->d_link[0], c->d_link[1],
+                      static_cast<void*>(c->d_uprev),
                       static_cast<void*>(c->d_partial), static_cast<void*>(c->d_result),
                       static_cast<void*>(c->d_stage)})
         if (ptr) ignore(hipFree(ptr));
@@ -201,6 +222,7 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
     c->nx = uint32_t(p->nx);
     c->ny = uint32_t(p->ny);
     c->n = uint32_t(n64);
+    c->ps = uint32_t((n64 + lbm::kChunk - 1) / lbm::kChunk * lbm::kChunk);
     lbm_status st = derive_globals(c);
     if (st != LBM_OK) {
         release(c);
@@ -284,7 +306,9 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
     for (int64_t k = 0; k < n_links; ++k) c->order[size_t(k)] = k;
     std::sort(c->order.begin(), c->order.end(), [&](int64_t a, int64_t b) { return keys[size_t(a)] < keys[size_t(b)]; });
     const uint32_t nchunks = (n + lbm::kChunk - 1) / lbm::kChunk;
-    std::vector<int32_t> chunk(nchunks + 1, 0);
+    c->nchunks = nchunks;
+    std::vector<int32_t>& chunk = c->chunk;
+    chunk.assign(nchunks + 1, 0);
     {
         int64_t acc = 0;
         for (uint32_t ch = 0; ch < nchunks; ++ch) {
@@ -305,6 +329,17 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
         dir[size_t(k)] = L.dir;
     }
 
+    // LDS staging of one block's wall links; fall back to smaller blocks for link-dense geometries
+    while (true) {
+        c->lds_links = std::max<uint32_t>(c->max_links_per_block(c->block), 1u);
+        if (lbm::step_lds_bytes(c->fp32(), c->lds_links) <= kMaxLds || c->block == 64) break;
+        c->block /= 2;
+    }
+    if (lbm::step_lds_bytes(c->fp32(), c->lds_links) > kMaxLds) {
+        release(c);
+        return fail(LBM_E_GEOMETRY, "%u wall links in one 64-site chunk exceed the LDS staging area", c->lds_links);
+    }
+
     // --- device allocations and uploads ---
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -318,6 +353,7 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
               alloc(reinterpret_cast<void**>(&c->d_coef64), sizeof(double) * 8 * nl) &&
               (!c->fp32() || alloc(reinterpret_cast<void**>(&c->d_coef32), sizeof(float) * 5 * nl)) &&
               alloc(&c->d_buf[0], c->pop_bytes()) && alloc(&c->d_buf[1], c->pop_bytes()) &&
+              alloc(&c->d_link[0], c->link_bytes()) && alloc(&c->d_link[1], c->link_bytes()) &&
               alloc(reinterpret_cast<void**>(&c->d_uprev), sizeof(double) * 2 * n) &&
               alloc(reinterpret_cast<void**>(&c->d_partial), sizeof(double) * 3 * lbm::residual_blocks(n)) &&
               alloc(reinterpret_cast<void**>(&c->d_result), sizeof(double) * 4) &&
@@ -359,7 +395,6 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
         a.L1 = c->L1;
         a.E = c->E;
         a.sq6pi = std::sqrt(6.0 / kPi);
-        a.rho0 = p->rho0;
         a.r_override = p->r_override;
         a.l_override = p->l_override;
         a.l_mode = p->l_mode;
@@ -451,6 +486,8 @@ lbm_status lbm_init_rest(lbm_ctx* c)
     // deviations from the rest state are zero; both time levels and the recorded velocity
     HIP_TRY(lbm::launch_fill_zero(c->d_buf[0], c->pop_bytes(), c->stream));
     HIP_TRY(lbm::launch_fill_zero(c->d_buf[1], c->pop_bytes(), c->stream));
+    HIP_TRY(lbm::launch_fill_zero(c->d_link[0], c->link_bytes(), c->stream));
+    HIP_TRY(lbm::launch_fill_zero(c->d_link[1], c->link_bytes(), c->stream));
     HIP_TRY(lbm::launch_fill_zero(c->d_uprev, sizeof(double) * 2 * c->n, c->stream));
     c->cur = 0;
     c->steps = 0;
@@ -476,70 +513,52 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, cons
         du = c->d_stage + c->n;
         dv = c->d_stage + 2 * size_t(c->n);
     }
-    HIP_TRY(lbm::launch_init_fields(c->fp32(), c->d_buf[0], c->d_flags, dr, du, dv, c->n, c->nx, c->ny, c->p.rho0,
-                                    c->p.ax, c->p.ay, c->stream));
+    HIP_TRY(lbm::launch_init_fields(c->fp32(), c->geo(), c->d_buf[0], c->d_link[0], dr, du, dv, c->p.rho0, c->p.ax,
+                                    c->p.ay, c->stream));
     if (!device_ptrs) HIP_TRY(hipStreamSynchronize(c->stream));  // the host arrays may go away
     return LBM_OK;
+}
+
+extern "C++" template <typename T>
+static lbm::StepArgs<T> step_args(const lbm_ctx* c, int src, int dst, const T* const* coef_rows)
+{
+    lbm::StepArgs<T> a{};
+    a.g = c->geo();
+    a.src = {static_cast<T*>(c->d_buf[src]), static_cast<T*>(c->d_link[src])};
+    a.dst = {static_cast<T*>(c->d_buf[dst]), static_cast<T*>(c->d_link[dst])};
+    a.coef = {coef_rows[0], coef_rows[1], coef_rows[2], coef_rows[3], coef_rows[4]};
+    a.ux_out = c->d_uprev;
+    a.uy_out = c->d_uprev + c->n;
+    a.lds_links = c->lds_links;
+    const double s_e = 1.0 / c->p.tau_e, s_eps = 1.0 / c->p.tau_eps, s_q = 1.0 / c->tau_q, s_s = 1.0 / c->tau_s;
+    a.rho0 = T(c->p.rho0);
+    a.ax = T(c->p.ax);
+    a.ay = T(c->p.ay);
+    a.s_e = T(s_e);
+    a.s_eps = T(s_eps);
+    a.s_q = T(s_q);
+    a.s_s = T(s_s);
+    a.c_e = T(1.0 - 0.5 * s_e);
+    a.c_eps = T(1.0 - 0.5 * s_eps);
+    a.c_q = T(1.0 - 0.5 * s_q);
+    a.c_s = T(1.0 - 0.5 * s_s);
+    return a;
 }
 
 static lbm_status step_once(lbm_ctx* c, bool write_u)
 {
     const int src = c->cur, dst = 1 - c->cur;
     const bool node = c->p.diffuse == LBM_DIFFUSE_NODE;
-    const double s_e = 1.0 / c->p.tau_e, s_eps = 1.0 / c->p.tau_eps, s_q = 1.0 / c->tau_q, s_s = 1.0 / c->tau_s;
     const size_t nl = size_t(std::max<int64_t>(c->n_links, 1));
     hipError_t e;
     if (c->fp32()) {
-        lbm::StepArgs<float> a{};
-        a.src = static_cast<const float*>(c->d_buf[src]);
-        a.dst = static_cast<float*>(c->d_buf[dst]);
-        a.flags = c->d_flags;
-        a.chunk_base = c->d_chunk;
-        a.coef = {c->d_coef32, c->d_coef32 + nl, c->d_coef32 + 2 * nl, c->d_coef32 + 3 * nl, c->d_coef32 + 4 * nl};
-        a.ux_out = c->d_uprev;
-        a.uy_out = c->d_uprev + c->n;
-        a.n = c->n;
-        a.nx = c->nx;
-        a.ny = c->ny;
-        a.remap_blocks = c->xcd_remap ? 1u : 0u;
-        a.rho0 = float(c->p.rho0);
-        a.ax = float(c->p.ax);
-        a.ay = float(c->p.ay);
-        a.s_e = float(s_e);
-        a.s_eps = float(s_eps);
-        a.s_q = float(s_q);
-        a.s_s = float(s_s);
-        a.c_e = float(1.0 - 0.5 * s_e);
-        a.c_eps = float(1.0 - 0.5 * s_eps);
-        a.c_q = float(1.0 - 0.5 * s_q);
-        a.c_s = float(1.0 - 0.5 * s_s);
-        e = lbm::launch_step_f32(a, c->block, write_u, node, c->stream);
+        const float* k32 = c->d_coef32;
+        const float* rows[5] = {k32, k32 + nl, k32 + 2 * nl, k32 + 3 * nl, k32 + 4 * nl};
+        e = lbm::launch_step_f32(step_args<float>(c, src, dst, rows), c->block, write_u, node, c->stream);
     } else {
-        lbm::StepArgs<double> a{};
-        a.src = static_cast<const double*>(c->d_buf[src]);
-        a.dst = static_cast<double*>(c->d_buf[dst]);
-        a.flags = c->d_flags;
-        a.chunk_base = c->d_chunk;
         const double* k64 = c->d_coef64;
-        a.coef = {k64 + 3 * nl, k64 + 4 * nl, k64 + 5 * nl, k64 + 6 * nl, k64 + 7 * nl};
-        a.ux_out = c->d_uprev;
-        a.uy_out = c->d_uprev + c->n;
-        a.n = c->n;
-        a.nx = c->nx;
-        a.ny = c->ny;
-        a.remap_blocks = c->xcd_remap ? 1u : 0u;
-        a.rho0 = c->p.rho0;
-        a.ax = c->p.ax;
-        a.ay = c->p.ay;
-        a.s_e = s_e;
-        a.s_eps = s_eps;
-        a.s_q = s_q;
-        a.s_s = s_s;
-        a.c_e = 1.0 - 0.5 * s_e;
-        a.c_eps = 1.0 - 0.5 * s_eps;
-        a.c_q = 1.0 - 0.5 * s_q;
-        a.c_s = 1.0 - 0.5 * s_s;
-        e = lbm::launch_step_f64(a, c->block, write_u, node, c->stream);
+        const double* rows[5] = {k64 + 3 * nl, k64 + 4 * nl, k64 + 5 * nl, k64 + 6 * nl, k64 + 7 * nl};
+        e = lbm::launch_step_f64(step_args<double>(c, src, dst, rows), c->block, write_u, node, c->stream);
     }
     if (e != hipSuccess) return fail(LBM_E_HIP, "step launch: %s", hipGetErrorString(e));
     c->cur = dst;
@@ -573,15 +592,15 @@ lbm_status lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, int32_t 
     if (!c || !rho || !ux || !uy) return fail(LBM_E_INVAL, "null argument");
     DeviceGuard g(c->device);
     if (device_ptrs) {
-        HIP_TRY(lbm::launch_moments(c->fp32(), c->d_buf[c->cur], c->d_flags, rho, ux, uy, c->n, c->nx, c->ny,
-                                    c->p.rho0, c->p.ax, c->p.ay, c->stream));
+        HIP_TRY(lbm::launch_moments(c->fp32(), c->geo(), c->d_buf[c->cur], c->d_link[c->cur], rho, ux, uy, c->p.rho0,
+                                    c->p.ax, c->p.ay, c->stream));
         return LBM_OK;
     }
     if (!c->d_stage && hipMalloc(reinterpret_cast<void**>(&c->d_stage), sizeof(double) * 3 * c->n) != hipSuccess)
         return fail(LBM_E_NOMEM, "staging buffer");
     double* s = c->d_stage;
-    HIP_TRY(lbm::launch_moments(c->fp32(), c->d_buf[c->cur], c->d_flags, s, s + c->n, s + 2 * size_t(c->n), c->n,
-                                c->nx, c->ny, c->p.rho0, c->p.ax, c->p.ay, c->stream));
+    HIP_TRY(lbm::launch_moments(c->fp32(), c->geo(), c->d_buf[c->cur], c->d_link[c->cur], s, s + c->n,
+                                s + 2 * size_t(c->n), c->p.rho0, c->p.ax, c->p.ay, c->stream));
     HIP_TRY(hipMemcpyAsync(rho, s, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(ux, s + c->n, sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(uy, s + 2 * size_t(c->n), sizeof(double) * c->n, hipMemcpyDeviceToHost, c->stream));
@@ -594,14 +613,12 @@ lbm_status lbm_residual(lbm_ctx* c, double* residual, double* mass)
     if (!c || !residual || !mass) return fail(LBM_E_INVAL, "null argument");
     DeviceGuard g(c->device);
     lbm::ReduceArgs a{};
-    a.src = c->d_buf[c->cur];
-    a.flags = c->d_flags;
+    a.g = c->geo();
+    a.pop = c->d_buf[c->cur];
+    a.link = c->d_link[c->cur];
     a.ux_prev = c->d_uprev;
     a.uy_prev = c->d_uprev + c->n;
     a.partial = c->d_partial;
-    a.n = c->n;
-    a.nx = c->nx;
-    a.ny = c->ny;
     a.rho0 = c->p.rho0;
     a.ax = c->p.ax;
     a.ay = c->p.ay;
@@ -633,13 +650,16 @@ lbm_status lbm_synchronize(lbm_ctx* c)
     return LBM_OK;
 }
 
-lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t xcd_remap)
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t block)
 {
     if (!c) return fail(LBM_E_INVAL, "null context");
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
         return fail(LBM_E_INVAL, "block %d not one of 64, 128, 256, 512, 1024", block);
+    const uint32_t links = std::max<uint32_t>(c->max_links_per_block(block), 1u);
+    if (lbm::step_lds_bytes(c->fp32(), links) > kMaxLds)
+        return fail(LBM_E_INVAL, "block %d would stage %u wall links, more than the LDS limit", block, links);
     c->block = block;
-    c->xcd_remap = xcd_remap != 0;
+    c->lds_links = links;
     return LBM_OK;
 }
 

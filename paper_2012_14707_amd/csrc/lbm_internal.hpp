@@ -13,8 +13,19 @@ namespace lbm {
 constexpr uint32_t kSolid = 0xFFu;
 
 // Sites are grouped in aligned chunks of one wavefront (64 sites); chunk_base[c] is the number
-// of wall links owned by sites < 64 c.  Links are stored sorted by (site, direction).
+// of wall links owned by sites < 64 c.  Links are stored sorted by (site, direction), so the
+// links of a site, of a wavefront and of a block are contiguous index ranges.
 constexpr int kChunk = 64;
+
+// Lattice geometry shared by every kernel.  Population plane i starts at element i * ps, with the
+// plane stride ps = n rounded up to a whole number of 64-site chunks, so that every plane starts on
+// a 128-byte line and a wavefront's 64 sites cover whole lines.
+struct Geo {
+    const uint8_t* flags;      // n
+    const int32_t* chunk_base; // nchunks + 1
+    uint32_t n, nx, ny, nchunks;
+    uint32_t ps;               // plane stride (elements)
+};
 
 // Per-link boundary coefficients in the storage precision, one array each (structure of arrays).
 template <typename T>
@@ -26,18 +37,24 @@ struct LinkCoef {
     const T* kappa;
 };
 
+// One time level of the state: nine population planes in pull layout (plane i at site y holds the
+// value site y + c_i receives) and, per wall link (x, d), the population opposite(d) that x
+// receives from the wall.
+template <typename T>
+struct Level {
+    T* pop;
+    T* link;
+};
+
 // Arguments of the fused collide-stream-boundary kernel.
 template <typename T>
 struct StepArgs {
-    const T* src;              // 9 planes of n values: slot (i, y) is pulled by site y + c_i
-    T* dst;                    // same layout, next time level
-    const uint8_t* flags;      // n
-    const int32_t* chunk_base; // ceil(n / 64) + 1
+    Geo g;
+    Level<T> src, dst;
     LinkCoef<T> coef;
     double* ux_out;            // n, written only when the kernel is asked to record u
     double* uy_out;
-    uint32_t n, nx, ny;
-    uint32_t remap_blocks;     // > 0: XCD-aware block remap over this many leading blocks
+    uint32_t lds_links;        // link slots of the LDS staging area (max links of one block)
     T rho0, ax, ay;
     T s_e, s_eps, s_q, s_s;    // relaxation rates 1/tau
     T c_e, c_eps, c_q, c_s;    // 1 - s/2 (forcing weights)
@@ -52,38 +69,38 @@ struct LinkInput {
 
 // Global parameters of the prescription needed by the per-link precompute.
 struct PrecomputeArgs {
-    double tau_s, L1, E, sq6pi, rho0;
+    double tau_s, L1, E, sq6pi;
     double r_override, l_override;
     int32_t l_mode, r_mode, diffuse;
     int64_t n_links;
 };
 
 struct ReduceArgs {
-    const void* src;
-    const uint8_t* flags;
+    Geo g;
+    const void* pop;
+    const void* link;
     const double* ux_prev;
     const double* uy_prev;
     double* partial;  // 3 per block
-    uint32_t n, nx, ny;
     double rho0, ax, ay;
 };
 
 // Launchers (lbm_kernels.hip).  All are asynchronous on `stream`.
 hipError_t launch_precompute(const LinkInput& in, const PrecomputeArgs& a, double* coef64, float* coef32,
                              hipStream_t stream);
+// Bytes of LDS one block of `block` threads needs for `max_links` wall links.
+size_t step_lds_bytes(bool fp32, uint32_t max_links);
 hipError_t launch_step_f64(const StepArgs<double>& a, int block, bool write_u, bool node_diffuse,
                            hipStream_t stream);
 hipError_t launch_step_f32(const StepArgs<float>& a, int block, bool write_u, bool node_diffuse,
                            hipStream_t stream);
 hipError_t launch_fill_zero(void* ptr, uint64_t bytes, hipStream_t stream);
-hipError_t launch_init_fields(bool fp32, void* dst, const uint8_t* flags, const double* rho, const double* ux,
-                              const double* uy, uint32_t n, uint32_t nx, uint32_t ny, double rho0, double ax,
-                              double ay, hipStream_t stream);
-hipError_t launch_moments(bool fp32, const void* src, const uint8_t* flags, double* rho, double* ux, double* uy,
-                          uint32_t n, uint32_t nx, uint32_t ny, double rho0, double ax, double ay,
-                          hipStream_t stream);
+hipError_t launch_init_fields(bool fp32, const Geo& g, void* pop, void* link, const double* rho, const double* ux,
+                              const double* uy, double rho0, double ax, double ay, hipStream_t stream);
+hipError_t launch_moments(bool fp32, const Geo& g, const void* pop, const void* link, double* rho, double* ux,
+                          double* uy, double rho0, double ax, double ay, hipStream_t stream);
 // Residual partial sums (|du|^2, |u|^2, sum of density deviations) and the fixed-order final
-// reduction into out[0..2].  Returns the number of partial blocks used.
+// reduction into out[0..2].
 hipError_t launch_residual(bool fp32, const ReduceArgs& a, double* out, hipStream_t stream);
 uint32_t residual_blocks(uint32_t n);
 

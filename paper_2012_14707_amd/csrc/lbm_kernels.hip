@@ -1,12 +1,28 @@
 // HIP kernels of liblbm for gfx950 (CDNA4, 64-wide wavefronts).
 //
 // Storage: populations as deviations g_i = f_i - w_i rho0 from the rest equilibrium, in nine
-// planes (structure of arrays) of n sites each, "pull" layout: plane i at site y holds the value
-// that site y + c_i receives at the next time level.  A fluid site therefore reads its nine
-// incoming populations at x - c_i (one coalesced, possibly one-element-shifted, load per plane)
-// and writes its nine outgoing values at its own index (fully coalesced).  For a wall link
-// (x, ibar) the incoming population i comes from the solid site x + c_ibar; the boundary rule of
-// Eq. (EqNewBDSC) writes it there, a slot no other site writes.
+// planes (structure of arrays) of n sites each, in "pull" layout: plane i at site y holds the
+// value that site y + c_i receives at the next time level.  A fluid site reads its nine incoming
+// populations at x - c_i (one coalesced, possibly one-element-shifted, load per plane) and writes
+// its outgoing post-collision values at its own index (fully coalesced).
+//
+// Stores are issued for whole 128-byte lines: a line that is only partly written costs a
+// read-modify-write in the memory system (measured: masking the stores of solid sites made a
+// step 50% slower than streaming every site, while masking their loads cost nothing).  So every
+// fluid site stores all nine planes (the value heading into a wall lands in a slot nobody reads),
+// and a solid site stores zeros into its own, never-read slots whenever its line also holds a
+// fluid site; lines that are entirely solid are skipped.
+//
+// Wall links: for a link (x, d) (x + c_d solid) the population i = opposite(d) that x receives at
+// t + 1 is given by the boundary rule of Eq. (EqNewBDSC).  It is kept in a per-link array, indexed
+// by the link's position in the (site, direction)-sorted link list, instead of in the solid
+// neighbour's plane slot: the pull then selects, per lane, the plane or the link array (one load
+// instruction per direction), and the boundary values are written link-parallel and coalesced.
+//
+// The boundary rule needs g_ibar(x, t), g'_i(x, t), g'_ibar(x, t), rho and the diffuse term, all
+// in the registers of the thread that collides x.  The thread deposits them in LDS; after a
+// barrier the block's threads walk the block's contiguous link range one link per thread, load
+// the link coefficients (coalesced) and store the boundary value (coalesced).
 //
 // The kernels are bound by HBM traffic (about 1-2 flop per byte); the 9x9 moment transform is
 // applied in closed form with additions only, not as a dense contraction.
@@ -23,7 +39,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
 }
 
-// Exclusive prefix over the wavefront of a per-lane count in [0, 15].
+// Exclusive prefix over the wavefront of a per-lane count in [0, 15]; every lane must take part.
 __device__ __forceinline__ uint32_t wave_prefix4(uint32_t v)
 {
     const uint64_t b0 = __ballot(v & 1u);
@@ -31,6 +47,26 @@ __device__ __forceinline__ uint32_t wave_prefix4(uint32_t v)
     const uint64_t b2 = __ballot(v & 4u);
     const uint64_t b3 = __ballot(v & 8u);
     return lanes_below(b0) + 2u * lanes_below(b1) + 4u * lanes_below(b2) + 8u * lanes_below(b3);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// True when the 128-byte line holding this lane's element (elements of `bytes` bytes, lines
+// aligned to the wavefront's first site) contains at least one lane with `any` set.  Every lane
+// must take part.
+__device__ __forceinline__ bool line_has(bool any, int bytes)
+{
+    const uint64_t m = __ballot(any);
+    const int per = 128 / bytes;  // lanes per line: 32 (fp32) or 16 (fp64)
+    const int lane = static_cast<int>(__lane_id());
+    const uint64_t grp = (per >= 64) ? ~0ull : (((1ull << per) - 1ull) << (lane & ~(per - 1)));
+    return (m & grp) != 0ull;
+}
+
+// Rank of link direction d (1..8) among the links of a site with flag byte fl.
+__device__ __forceinline__ uint32_t rank_of(uint32_t fl, int d)
+{
+    return static_cast<uint32_t>(__popc(fl & ((1u << (d - 1)) - 1u)));
 }
 
 struct Nbr {
@@ -50,6 +86,22 @@ __device__ __forceinline__ Nbr neighbours(uint32_t s, uint32_t nx, uint32_t ny)
     b.rowm = ym * nx;
     b.rowp = yp * nx;
     return b;
+}
+
+// Flag byte of site s and the index of its first wall link.  Lanes past the end read as solid.
+struct SiteLinks {
+    uint32_t fl, k0;
+};
+
+__device__ __forceinline__ SiteLinks site_links(const Geo& g, uint32_t s)
+{
+    SiteLinks r;
+    r.fl = (s < g.n) ? static_cast<uint32_t>(g.flags[s]) : kSolid;
+    const uint32_t nlink = (r.fl != kSolid) ? static_cast<uint32_t>(__popc(r.fl)) : 0u;
+    const uint32_t pre = wave_prefix4(nlink);
+    // waves past the end read the final entry (index nchunks)
+    r.k0 = static_cast<uint32_t>(g.chunk_base[uniform(min(s / kChunk, g.nchunks))]) + pre;
+    return r;
 }
 
 // 1/9 and 1/6 as an unevaluated sum hi + lo of two values of the storage type.
@@ -73,27 +125,34 @@ struct Third<float> {
 template <typename T>
 __device__ __forceinline__ T split_mul(T x, T hi, T lo) { return fma(x, hi, x * lo); }
 
-// The nine pulled populations g_i(x, t) (D2Q9 order of Eq. (Eq3)).
+// The nine incoming populations g_i(x, t) (D2Q9 order of Eq. (Eq3)).
 template <typename T>
 struct Pop {
     T g0, g1, g2, g3, g4, g5, g6, g7, g8;
 };
 
+// Population i of site s: from plane i at s - c_i, or from the link array when the upstream
+// neighbour is a wall (link toward d = opposite(i)).  One load with a per-lane address.
+#define LBM_PULL(I, D, UP)                                                                     \
+    ((fl & (1u << ((D) - 1))) ? lnk[k0 + rank_of(fl, (D))] : pop[(I) * ps + (UP)])
+
 template <typename T>
-__device__ __forceinline__ Pop<T> pull(const T* __restrict__ src, uint64_t n, uint32_t s, const Nbr& b)
+__device__ __forceinline__ Pop<T> pull(const T* __restrict__ pop, const T* __restrict__ lnk, uint64_t ps, uint32_t s,
+                                       const Nbr& b, uint32_t fl, uint32_t k0)
 {
     Pop<T> p;
-    p.g0 = src[s];
-    p.g1 = src[1 * n + b.row + b.xm];   // from (x-1, y)
-    p.g2 = src[2 * n + b.rowm + b.x];   // from (x, y-1)
-    p.g3 = src[3 * n + b.row + b.xp];   // from (x+1, y)
-    p.g4 = src[4 * n + b.rowp + b.x];   // from (x, y+1)
-    p.g5 = src[5 * n + b.rowm + b.xm];  // from (x-1, y-1)
-    p.g6 = src[6 * n + b.rowm + b.xp];  // from (x+1, y-1)
-    p.g7 = src[7 * n + b.rowp + b.xp];  // from (x+1, y+1)
-    p.g8 = src[8 * n + b.rowp + b.xm];  // from (x-1, y+1)
+    p.g0 = pop[s];
+    p.g1 = LBM_PULL(1, 3, b.row + b.xm);   // from (x-1, y)
+    p.g2 = LBM_PULL(2, 4, b.rowm + b.x);   // from (x, y-1)
+    p.g3 = LBM_PULL(3, 1, b.row + b.xp);   // from (x+1, y)
+    p.g4 = LBM_PULL(4, 2, b.rowp + b.x);   // from (x, y+1)
+    p.g5 = LBM_PULL(5, 7, b.rowm + b.xm);  // from (x-1, y-1)
+    p.g6 = LBM_PULL(6, 8, b.rowm + b.xp);  // from (x+1, y-1)
+    p.g7 = LBM_PULL(7, 5, b.rowp + b.xp);  // from (x+1, y+1)
+    p.g8 = LBM_PULL(8, 6, b.rowp + b.xm);  // from (x-1, y+1)
     return p;
 }
+#undef LBM_PULL
 
 // Density deviation and half-force velocity (Eq. (FluidMacr)) accumulated in fp64, for the
 // residual, the recorded velocity and the moments output.
@@ -111,155 +170,165 @@ __device__ __forceinline__ void macro_fp64(const Pop<T>& p, double rho0, double 
     uy = (jy + 0.5 * rho * ay) / rho;
 }
 
-// One boundary value of Eq. (EqNewBDSC) in deviation form (see the header of this file):
-//   g_i(x_f, t+1) = a1 g_ibar + a2 g'_i + a3 g'_ibar + beta rho + kappa w_i (drho + rho phi_i(u)),
-// phi_i(u) = 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u^2, and the rho phi term only in the node reading.
-template <typename T, bool NODE>
-__device__ __forceinline__ T boundary_value(const LinkCoef<T>& c, uint32_t k, T g_ibar, T h_i, T h_ibar, T rho,
-                                            T dr, T w, T cu, T u2)
-{
-    T diffuse = dr;
-    if (NODE) diffuse += rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * u2);
-    return c.a1[k] * g_ibar + c.a2[k] * h_i + c.a3[k] * h_ibar + c.beta[k] * rho + c.kappa[k] * (w * diffuse);
-}
+// LDS staging of one link's operands: five arrays of lds_links entries.
+template <typename T>
+struct LinkStage {
+    T* gb;   // g_ibar(x, t), pre-collision, toward the wall
+    T* hi;   // g'_i(x, t), post-collision, away from the wall
+    T* hb;   // g'_ibar(x, t)
+    T* rho;  // rho(x, t)
+    T* dif;  // w_i (drho + rho phi_i(u)) in the node reading, w_i drho in the wall reading
+};
 
 template <typename T, bool WRITE_U, bool NODE, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
 {
-    uint32_t blk = blockIdx.x;
-    if (blk < a.remap_blocks) blk = (blk & 7u) * (a.remap_blocks >> 3) + (blk >> 3);
-    const uint32_t s = blk * BLOCK + threadIdx.x;
-    const uint64_t n = a.n;
-    const uint32_t fl = (s < a.n) ? static_cast<uint32_t>(a.flags[s]) : kSolid;
-    const bool fluid = fl != kSolid;
-    const uint32_t nlink = fluid ? static_cast<uint32_t>(__popc(fl)) : 0u;
-    const uint32_t pre = wave_prefix4(nlink);  // every lane of the wave takes part
-    if (!fluid) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Geo& g = a.g;
+    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
+    // link range of this block (uniform, scalar loads)
+    const uint32_t c0 = blockIdx.x * (BLOCK / kChunk);
+    const uint32_t c1 = min(c0 + BLOCK / kChunk, g.nchunks);
+    const uint32_t kblk = static_cast<uint32_t>(g.chunk_base[c0]);
+    const uint32_t nl_blk = static_cast<uint32_t>(g.chunk_base[c1]) - kblk;
+    const SiteLinks sl = site_links(g, s);
+    const uint32_t fl = sl.fl, k0 = sl.k0;
+    const uint64_t ps = g.ps;
+    const bool store_line = line_has(fl != kSolid, sizeof(T));
 
-    const Nbr b = neighbours(s, a.nx, a.ny);
-    const Pop<T> p = pull(a.src, n, s, b);
-    const T g0 = p.g0, g1 = p.g1, g2 = p.g2, g3 = p.g3, g4 = p.g4, g5 = p.g5, g6 = p.g6, g7 = p.g7, g8 = p.g8;
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const LinkStage<T> st{lds, lds + a.lds_links, lds + 2 * a.lds_links, lds + 3 * a.lds_links,
+                          lds + 4 * a.lds_links};
 
-    if (WRITE_U) {
-        double dr_d, rho_d, ux_d, uy_d;
-        macro_fp64(p, static_cast<double>(a.rho0), static_cast<double>(a.ax), static_cast<double>(a.ay), dr_d,
-                   rho_d, ux_d, uy_d);
-        a.ux_out[s] = ux_d;
-        a.uy_out[s] = uy_d;
+    if (fl != kSolid) {
+        const Nbr b = neighbours(s, g.nx, g.ny);
+        const Pop<T> p = pull(a.src.pop, a.src.link, ps, s, b, fl, k0);
+        const T g0 = p.g0, g1 = p.g1, g2 = p.g2, g3 = p.g3, g4 = p.g4, g5 = p.g5, g6 = p.g6, g7 = p.g7,
+                g8 = p.g8;
+
+        if (WRITE_U) {
+            double dr_d, rho_d, ux_d, uy_d;
+            macro_fp64(p, static_cast<double>(a.rho0), static_cast<double>(a.ax), static_cast<double>(a.ay),
+                       dr_d, rho_d, ux_d, uy_d);
+            a.ux_out[s] = ux_d;
+            a.uy_out[s] = uy_d;
+        }
+
+        // conserved moments and half-force velocity, Eq. (FluidMacr)
+        const T s14 = (g1 + g2) + (g3 + g4);
+        const T s58 = (g5 + g6) + (g7 + g8);
+        const T dr = g0 + s14 + s58;
+        const T rho = a.rho0 + dr;
+        const T jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
+        const T jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
+        const T irho = T(1) / rho;
+        const T ux = (jx + T(0.5) * rho * a.ax) * irho;
+        const T uy = (jy + T(0.5) * rho * a.ay) * irho;
+        const T u2 = ux * ux + uy * uy;
+
+        // non-conserved moments m = M g (rows of M in Sec. II)
+        const T e = T(-4) * g0 - s14 + T(2) * s58;
+        const T eps = T(4) * g0 - T(2) * s14 + s58;
+        const T qx = T(-2) * (g1 - g3) + ((g5 - g6) + (g8 - g7));
+        const T qy = T(-2) * (g2 - g4) + ((g5 + g6) - (g7 + g8));
+        const T pxx = (g1 + g3) - (g2 + g4);
+        const T pxy = (g5 + g7) - (g6 + g8);
+
+        // equilibria of Eq. (LBEequi) in moment space (deviation from the rest state) and the Guo
+        // forcing moments M Fbar of Eq. (LBEforce): (0, 6 rho u.a, -6 rho u.a, rho a_x, -rho a_x,
+        // rho a_y, -rho a_y, 2 rho (u_x a_x - u_y a_y), rho (u_x a_y + u_y a_x))
+        const T ru2 = T(3) * rho * u2;
+        const T ua6 = T(6) * rho * (ux * a.ax + uy * a.ay);
+        const T ep = e - a.s_e * (e - (T(-2) * dr + ru2)) + a.c_e * ua6;
+        const T epsp = eps - a.s_eps * (eps - (dr - ru2)) - a.c_eps * ua6;
+        const T qxp = qx - a.s_q * (qx + rho * ux) - a.c_q * (rho * a.ax);
+        const T qyp = qy - a.s_q * (qy + rho * uy) - a.c_q * (rho * a.ay);
+        const T pxxp =
+            pxx - a.s_s * (pxx - rho * (ux * ux - uy * uy)) + a.c_s * (T(2) * rho * (ux * a.ax - uy * a.ay));
+        const T pxyp = pxy - a.s_s * (pxy - rho * (ux * uy)) + a.c_s * (rho * (ux * a.ay + uy * a.ax));
+        // conserved: rho' = rho; j' = j + rho a exactly (the tau_j relaxation and forcing cancel)
+        const T jxp = jx + rho * a.ax;
+        const T jyp = jy + rho * a.ay;
+
+        // f' = M^-1 m' with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+        // The conserved moments (rho, j) never relax, so a rounded constant 1/9 or 1/6 would scale
+        // mass and momentum by (1 + its rounding error) at every collision and the bias would grow
+        // over the whole run; they are divided with a two-term constant (error below one ulp,
+        // unbiased).
+        const T r0 = split_mul(dr, Third<T>::c9_hi, Third<T>::c9_lo);
+        const T r1 = ep * T(1.0 / 36.0);
+        const T r2 = epsp * T(1.0 / 36.0);
+        const T r3 = split_mul(jxp, Third<T>::c6_hi, Third<T>::c6_lo);
+        const T r4 = qxp * T(1.0 / 12.0);
+        const T r5 = split_mul(jyp, Third<T>::c6_hi, Third<T>::c6_lo);
+        const T r6 = qyp * T(1.0 / 12.0);
+        const T r7 = pxxp * T(0.25);
+        const T r8 = pxyp * T(0.25);
+        const T A = r0 - r1 - T(2) * r2;
+        const T B = r0 + T(2) * r1 + r2;
+        const T X = r3 - T(2) * r4, Y = r5 - T(2) * r6;
+        const T XD = r3 + r4, YD = r5 + r6;
+        const T h0 = r0 - T(4) * r1 + T(4) * r2;
+        const T h1 = A + X + r7;
+        const T h2 = A + Y - r7;
+        const T h3 = A - X + r7;
+        const T h4 = A - Y - r7;
+        const T h5 = B + XD + YD + r8;
+        const T h6 = B - XD + YD - r8;
+        const T h7 = B - XD - YD + r8;
+        const T h8 = B + XD - YD - r8;
+
+        // Post-collision values leave along c_i and are pulled by x + c_i (the ones heading into
+        // a wall are stored too, into slots nobody reads, to keep the lines whole).
+        T* __restrict__ dst = a.dst.pop;
+        dst[s] = h0;
+        dst[1 * ps + s] = h1;
+        dst[2 * ps + s] = h2;
+        dst[3 * ps + s] = h3;
+        dst[4 * ps + s] = h4;
+        dst[5 * ps + s] = h5;
+        dst[6 * ps + s] = h6;
+        dst[7 * ps + s] = h7;
+        dst[8 * ps + s] = h8;
+
+        if (fl) {
+            // operands of Eq. (EqNewBDSC) for each wall link (x, d); the unknown is i = opposite(d)
+            const T w1 = T(1.0 / 9.0), w5 = T(1.0 / 36.0);
+            const uint32_t j0 = k0 - kblk;
+            auto deposit = [&](int d, T gb, T hi, T hb, T w, T cu) {
+                const uint32_t j = j0 + rank_of(fl, d);
+                T dif = dr;
+                if (NODE) dif += rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * u2);
+                st.gb[j] = gb;
+                st.hi[j] = hi;
+                st.hb[j] = hb;
+                st.rho[j] = rho;
+                st.dif[j] = w * dif;
+            };
+            if (fl & 0x01u) deposit(1, g1, h3, h1, w1, -ux);        // toward E, unknown W
+            if (fl & 0x02u) deposit(2, g2, h4, h2, w1, -uy);        // toward N, unknown S
+            if (fl & 0x04u) deposit(3, g3, h1, h3, w1, ux);         // toward W, unknown E
+            if (fl & 0x08u) deposit(4, g4, h2, h4, w1, uy);         // toward S, unknown N
+            if (fl & 0x10u) deposit(5, g5, h7, h5, w5, -ux - uy);   // toward NE, unknown SW
+            if (fl & 0x20u) deposit(6, g6, h8, h6, w5, ux - uy);    // toward NW, unknown SE
+            if (fl & 0x40u) deposit(7, g7, h5, h7, w5, ux + uy);    // toward SW, unknown NE
+            if (fl & 0x80u) deposit(8, g8, h6, h8, w5, -ux + uy);   // toward SE, unknown NW
+        }
+    } else if (store_line && s < g.n) {
+        T* __restrict__ dst = a.dst.pop;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) dst[i * ps + s] = T(0);
     }
 
-    // conserved moments and half-force velocity, Eq. (FluidMacr)
-    const T s14 = (g1 + g2) + (g3 + g4);
-    const T s58 = (g5 + g6) + (g7 + g8);
-    const T dr = g0 + s14 + s58;
-    const T rho = a.rho0 + dr;
-    const T jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
-    const T jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
-    const T irho = T(1) / rho;
-    const T ux = (jx + T(0.5) * rho * a.ax) * irho;
-    const T uy = (jy + T(0.5) * rho * a.ay) * irho;
-    const T u2 = ux * ux + uy * uy;
-
-    // non-conserved moments m = M g (rows of M in Sec. II)
-    const T e = T(-4) * g0 - s14 + T(2) * s58;
-    const T eps = T(4) * g0 - T(2) * s14 + s58;
-    const T qx = T(-2) * (g1 - g3) + ((g5 - g6) + (g8 - g7));
-    const T qy = T(-2) * (g2 - g4) + ((g5 + g6) - (g7 + g8));
-    const T pxx = (g1 + g3) - (g2 + g4);
-    const T pxy = (g5 + g7) - (g6 + g8);
-
-    // equilibria of Eq. (LBEequi) in moment space (deviation from the rest state) and the Guo
-    // forcing moments M Fbar of Eq. (LBEforce): (0, 6 rho u.a, -6 rho u.a, rho a_x, -rho a_x,
-    // rho a_y, -rho a_y, 2 rho (u_x a_x - u_y a_y), rho (u_x a_y + u_y a_x))
-    const T ru2 = T(3) * rho * u2;
-    const T ua6 = T(6) * rho * (ux * a.ax + uy * a.ay);
-    const T ep = e - a.s_e * (e - (T(-2) * dr + ru2)) + a.c_e * ua6;
-    const T epsp = eps - a.s_eps * (eps - (dr - ru2)) - a.c_eps * ua6;
-    const T qxp = qx - a.s_q * (qx + rho * ux) - a.c_q * (rho * a.ax);
-    const T qyp = qy - a.s_q * (qy + rho * uy) - a.c_q * (rho * a.ay);
-    const T pxxp = pxx - a.s_s * (pxx - rho * (ux * ux - uy * uy)) + a.c_s * (T(2) * rho * (ux * a.ax - uy * a.ay));
-    const T pxyp = pxy - a.s_s * (pxy - rho * (ux * uy)) + a.c_s * (rho * (ux * a.ay + uy * a.ax));
-    // conserved: rho' = rho; j' = j + rho a exactly (the tau_j relaxation and forcing cancel)
-    const T jxp = jx + rho * a.ax;
-    const T jyp = jy + rho * a.ay;
-
-    // f' = M^-1 m' with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
-    // The conserved moments (rho, j) never relax, so a rounded constant 1/9 or 1/6 would scale
-    // mass and momentum by (1 + its rounding error) at every collision and the bias would grow
-    // over the whole run; they are divided with a two-term constant (error below one ulp, unbiased).
-    const T r0 = split_mul(dr, Third<T>::c9_hi, Third<T>::c9_lo);
-    const T r1 = ep * T(1.0 / 36.0);
-    const T r2 = epsp * T(1.0 / 36.0);
-    const T r3 = split_mul(jxp, Third<T>::c6_hi, Third<T>::c6_lo);
-    const T r4 = qxp * T(1.0 / 12.0);
-    const T r5 = split_mul(jyp, Third<T>::c6_hi, Third<T>::c6_lo);
-    const T r6 = qyp * T(1.0 / 12.0);
-    const T r7 = pxxp * T(0.25);
-    const T r8 = pxyp * T(0.25);
-    const T A = r0 - r1 - T(2) * r2;
-    const T B = r0 + T(2) * r1 + r2;
-    const T X = r3 - T(2) * r4, Y = r5 - T(2) * r6;
-    const T XD = r3 + r4, YD = r5 + r6;
-    const T h0 = r0 - T(4) * r1 + T(4) * r2;
-    const T h1 = A + X + r7;
-    const T h2 = A + Y - r7;
-    const T h3 = A - X + r7;
-    const T h4 = A - Y - r7;
-    const T h5 = B + XD + YD + r8;
-    const T h6 = B - XD + YD - r8;
-    const T h7 = B - XD - YD + r8;
-    const T h8 = B + XD - YD - r8;
-
-    T* __restrict__ dst = a.dst;
-    // Post-collision values leave along c_i and are pulled by x + c_i next step; the ones that
-    // would enter a solid site are not needed and are not stored.
-    dst[s] = h0;
-    if (!(fl & 0x01u)) dst[1 * n + s] = h1;
-    if (!(fl & 0x02u)) dst[2 * n + s] = h2;
-    if (!(fl & 0x04u)) dst[3 * n + s] = h3;
-    if (!(fl & 0x08u)) dst[4 * n + s] = h4;
-    if (!(fl & 0x10u)) dst[5 * n + s] = h5;
-    if (!(fl & 0x20u)) dst[6 * n + s] = h6;
-    if (!(fl & 0x40u)) dst[7 * n + s] = h7;
-    if (!(fl & 0x80u)) dst[8 * n + s] = h8;
-
-    if (fl) {
-        // wall links of this node, in direction order; link d (toward the wall) fills the unknown
-        // i = opposite(d) at the solid site x + c_d
-        uint32_t k = static_cast<uint32_t>(a.chunk_base[s / kChunk]) + pre;
-        const T w1 = T(1.0 / 9.0), w5 = T(1.0 / 36.0);
-        const LinkCoef<T> c = a.coef;
-        if (fl & 0x01u) {  // d = 1 (E), unknown i = 3 (W): c_i.u = -ux
-            dst[3 * n + b.row + b.xp] = boundary_value<T, NODE>(c, k, g1, h3, h1, rho, dr, w1, -ux, u2);
-            ++k;
-        }
-        if (fl & 0x02u) {  // d = 2 (N), i = 4 (S)
-            dst[4 * n + b.rowp + b.x] = boundary_value<T, NODE>(c, k, g2, h4, h2, rho, dr, w1, -uy, u2);
-            ++k;
-        }
-        if (fl & 0x04u) {  // d = 3 (W), i = 1 (E)
-            dst[1 * n + b.row + b.xm] = boundary_value<T, NODE>(c, k, g3, h1, h3, rho, dr, w1, ux, u2);
-            ++k;
-        }
-        if (fl & 0x08u) {  // d = 4 (S), i = 2 (N)
-            dst[2 * n + b.rowm + b.x] = boundary_value<T, NODE>(c, k, g4, h2, h4, rho, dr, w1, uy, u2);
-            ++k;
-        }
-        if (fl & 0x10u) {  // d = 5 (NE), i = 7 (SW)
-            dst[7 * n + b.rowp + b.xp] = boundary_value<T, NODE>(c, k, g5, h7, h5, rho, dr, w5, -ux - uy, u2);
-            ++k;
-        }
-        if (fl & 0x20u) {  // d = 6 (NW), i = 8 (SE)
-            dst[8 * n + b.rowp + b.xm] = boundary_value<T, NODE>(c, k, g6, h8, h6, rho, dr, w5, ux - uy, u2);
-            ++k;
-        }
-        if (fl & 0x40u) {  // d = 7 (SW), i = 5 (NE)
-            dst[5 * n + b.rowm + b.xm] = boundary_value<T, NODE>(c, k, g7, h5, h7, rho, dr, w5, ux + uy, u2);
-            ++k;
-        }
-        if (fl & 0x80u) {  // d = 8 (SE), i = 6 (NW)
-            dst[6 * n + b.rowm + b.xp] = boundary_value<T, NODE>(c, k, g8, h6, h8, rho, dr, w5, -ux + uy, u2);
-        }
+    if (nl_blk == 0) return;  // block-uniform
+    __syncthreads();
+    // link-parallel phase: Eq. (EqNewBDSC) in deviation form,
+    //   g_i(x, t+1) = a1 g_ibar + a2 g'_i + a3 g'_ibar + beta rho + kappa w_i (drho + rho phi_i(u))
+    const LinkCoef<T> c = a.coef;
+    for (uint32_t j = threadIdx.x; j < nl_blk; j += BLOCK) {
+        const uint32_t k = kblk + j;
+        a.dst.link[k] = c.a1[k] * st.gb[j] + c.a2[k] * st.hi[j] + c.a3[k] * st.hb[j] + c.beta[k] * st.rho[j] +
+                        c.kappa[k] * st.dif[j];
     }
 }
 
@@ -351,49 +420,58 @@ __global__ void __launch_bounds__(256) k_fill_zero_bytes(uint8_t* p, uint64_t n)
     if (i < n) p[i] = 0;
 }
 
-// f_i(x, 0) = f_i^eq(rho, u - a/2): stored at slot (i, x - c_i) as the deviation
-// w_i (rho - rho0) + w_i rho (3 c.v + 4.5 (c.v)^2 - 1.5 v^2), v = u - a/2.
+// f_i(x, 0) = f_i^eq(rho, u - a/2) as the deviation w_i (rho - rho0) + w_i rho (3 c.v + 4.5 (c.v)^2
+// - 1.5 v^2), v = u - a/2, stored where site x pulls it from: plane i at x - c_i, or the link
+// array for populations that come from a wall.
 template <typename T>
-__global__ void __launch_bounds__(256) k_init_fields(T* dst, const uint8_t* flags, const double* rho_in,
-                                                     const double* ux_in, const double* uy_in, uint32_t n,
-                                                     uint32_t nx, uint32_t ny, double rho0, double ax, double ay)
+__global__ void __launch_bounds__(256) k_init_fields(const Geo g, T* pop, T* lnk, const double* rho_in,
+                                                     const double* ux_in, const double* uy_in, double rho0,
+                                                     double ax, double ay)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n || flags[s] == kSolid) return;
-    const Nbr b = neighbours(s, nx, ny);
+    const SiteLinks sl = site_links(g, s);
+    const uint32_t fl = sl.fl, k0 = sl.k0;
+    if (fl == kSolid) return;
+    const Nbr b = neighbours(s, g.nx, g.ny);
     const double rho = rho_in[s];
     const double vx = ux_in[s] - 0.5 * ax, vy = uy_in[s] - 0.5 * ay;
     const double v2 = vx * vx + vy * vy;
-    const uint64_t N = n;
+    const uint64_t N = g.ps;
     auto dev = [&](double w, double cv) {
         return static_cast<T>(w * (rho - rho0) + w * rho * (3.0 * cv + 4.5 * cv * cv - 1.5 * v2));
     };
-    dst[s] = dev(4.0 / 9.0, 0.0);
-    dst[1 * N + b.row + b.xm] = dev(1.0 / 9.0, vx);
-    dst[2 * N + b.rowm + b.x] = dev(1.0 / 9.0, vy);
-    dst[3 * N + b.row + b.xp] = dev(1.0 / 9.0, -vx);
-    dst[4 * N + b.rowp + b.x] = dev(1.0 / 9.0, -vy);
-    dst[5 * N + b.rowm + b.xm] = dev(1.0 / 36.0, vx + vy);
-    dst[6 * N + b.rowm + b.xp] = dev(1.0 / 36.0, -vx + vy);
-    dst[7 * N + b.rowp + b.xp] = dev(1.0 / 36.0, -vx - vy);
-    dst[8 * N + b.rowp + b.xm] = dev(1.0 / 36.0, vx - vy);
+    auto put = [&](int i, int d, uint32_t up, T v) {
+        if (fl & (1u << (d - 1)))
+            lnk[k0 + rank_of(fl, d)] = v;
+        else
+            pop[i * N + up] = v;
+    };
+    pop[s] = dev(4.0 / 9.0, 0.0);
+    put(1, 3, b.row + b.xm, dev(1.0 / 9.0, vx));
+    put(2, 4, b.rowm + b.x, dev(1.0 / 9.0, vy));
+    put(3, 1, b.row + b.xp, dev(1.0 / 9.0, -vx));
+    put(4, 2, b.rowp + b.x, dev(1.0 / 9.0, -vy));
+    put(5, 7, b.rowm + b.xm, dev(1.0 / 36.0, vx + vy));
+    put(6, 8, b.rowm + b.xp, dev(1.0 / 36.0, -vx + vy));
+    put(7, 5, b.rowp + b.xp, dev(1.0 / 36.0, -vx - vy));
+    put(8, 6, b.rowp + b.xm, dev(1.0 / 36.0, vx - vy));
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_moments(const T* src, const uint8_t* flags, double* rho, double* ux,
-                                                 double* uy, uint32_t n, uint32_t nx, uint32_t ny, double rho0,
-                                                 double ax, double ay)
+__global__ void __launch_bounds__(256) k_moments(const Geo g, const T* pop, const T* lnk, double* rho, double* ux,
+                                                 double* uy, double rho0, double ax, double ay)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    if (flags[s] == kSolid) {
+    const SiteLinks sl = site_links(g, s);
+    if (s >= g.n) return;
+    if (sl.fl == kSolid) {
         rho[s] = 0.0;
         ux[s] = 0.0;
         uy[s] = 0.0;
         return;
     }
-    const Nbr b = neighbours(s, nx, ny);
-    const Pop<T> p = pull(src, n, s, b);
+    const Nbr b = neighbours(s, g.nx, g.ny);
+    const Pop<T> p = pull(pop, lnk, g.ps, s, b, sl.fl, sl.k0);
     double dr, r, u, v;
     macro_fp64(p, rho0, ax, ay, dr, r, u, v);
     rho[s] = r;
@@ -435,17 +513,21 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c)
     }
 }
 
-// Grid-stride partial sums: sum |u - u_prev|^2, sum |u|^2, sum (rho - rho0) over fluid sites.
+// Block-strided partial sums: sum |u - u_prev|^2, sum |u|^2, sum (rho - rho0) over fluid sites.
+// The loop bound is block-uniform so that every lane takes part in the link prefix.
 template <typename T>
 __global__ void __launch_bounds__(kRedBlock) k_residual_partial(const ReduceArgs a)
 {
-    const T* src = static_cast<const T*>(a.src);
+    const T* pop = static_cast<const T*>(a.pop);
+    const T* lnk = static_cast<const T*>(a.link);
     double s_du = 0.0, s_u = 0.0, s_dr = 0.0;
     const uint32_t stride = gridDim.x * kRedBlock;
-    for (uint32_t s = blockIdx.x * kRedBlock + threadIdx.x; s < a.n; s += stride) {
-        if (a.flags[s] == kSolid) continue;
-        const Nbr b = neighbours(s, a.nx, a.ny);
-        const Pop<T> p = pull(src, a.n, s, b);
+    for (uint32_t base = blockIdx.x * kRedBlock; base < a.g.n; base += stride) {
+        const uint32_t s = base + threadIdx.x;
+        const SiteLinks sl = site_links(a.g, s);
+        if (sl.fl == kSolid) continue;
+        const Nbr b = neighbours(s, a.g.nx, a.g.ny);
+        const Pop<T> p = pull(pop, lnk, a.g.ps, s, b, sl.fl, sl.k0);
         double dr, r, u, v;
         macro_fp64(p, a.rho0, a.ax, a.ay, dr, r, u, v);
         const double du = u - a.ux_prev[s], dv = v - a.uy_prev[s];
@@ -482,26 +564,25 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return static_cast<uint32_t>(
 template <typename T, int BLOCK>
 hipError_t launch_step_block(const StepArgs<T>& a, bool write_u, bool node, hipStream_t stream)
 {
-    const uint32_t grid = ceil_div(a.n, BLOCK);
+    const uint32_t grid = ceil_div(a.g.n, BLOCK);
+    const size_t lds = 5 * sizeof(T) * a.lds_links;
     if (write_u) {
         if (node)
-            hipLaunchKernelGGL((k_step<T, true, true, BLOCK>), dim3(grid), dim3(BLOCK), 0, stream, a);
+            hipLaunchKernelGGL((k_step<T, true, true, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
         else
-            hipLaunchKernelGGL((k_step<T, true, false, BLOCK>), dim3(grid), dim3(BLOCK), 0, stream, a);
+            hipLaunchKernelGGL((k_step<T, true, false, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
     } else {
         if (node)
-            hipLaunchKernelGGL((k_step<T, false, true, BLOCK>), dim3(grid), dim3(BLOCK), 0, stream, a);
+            hipLaunchKernelGGL((k_step<T, false, true, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
         else
-            hipLaunchKernelGGL((k_step<T, false, false, BLOCK>), dim3(grid), dim3(BLOCK), 0, stream, a);
+            hipLaunchKernelGGL((k_step<T, false, false, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_step_t(StepArgs<T> a, int block, bool write_u, bool node, hipStream_t stream)
+hipError_t launch_step_t(const StepArgs<T>& a, int block, bool write_u, bool node, hipStream_t stream)
 {
-    // the XCD remap covers the leading multiple of 8 blocks
-    if (a.remap_blocks) a.remap_blocks = (ceil_div(a.n, block) / 8u) * 8u;
     switch (block) {
     case 64: return launch_step_block<T, 64>(a, write_u, node, stream);
     case 128: return launch_step_block<T, 128>(a, write_u, node, stream);
@@ -512,6 +593,8 @@ hipError_t launch_step_t(StepArgs<T> a, int block, bool write_u, bool node, hipS
 }
 
 }  // namespace
+
+size_t step_lds_bytes(bool fp32, uint32_t max_links) { return 5 * (fp32 ? 4 : 8) * size_t(max_links); }
 
 hipError_t launch_step_f64(const StepArgs<double>& a, int block, bool write_u, bool node, hipStream_t stream)
 {
@@ -545,31 +628,29 @@ hipError_t launch_fill_zero(void* ptr, uint64_t bytes, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_init_fields(bool fp32, void* dst, const uint8_t* flags, const double* rho, const double* ux,
-                              const double* uy, uint32_t n, uint32_t nx, uint32_t ny, double rho0, double ax,
-                              double ay, hipStream_t stream)
+hipError_t launch_init_fields(bool fp32, const Geo& g, void* pop, void* link, const double* rho, const double* ux,
+                              const double* uy, double rho0, double ax, double ay, hipStream_t stream)
 {
-    const dim3 grid(ceil_div(n, 256)), blk(256);
+    const dim3 grid(ceil_div(g.n, 256)), blk(256);
     if (fp32)
-        hipLaunchKernelGGL(k_init_fields<float>, grid, blk, 0, stream, static_cast<float*>(dst), flags, rho, ux, uy,
-                           n, nx, ny, rho0, ax, ay);
+        hipLaunchKernelGGL(k_init_fields<float>, grid, blk, 0, stream, g, static_cast<float*>(pop),
+                           static_cast<float*>(link), rho, ux, uy, rho0, ax, ay);
     else
-        hipLaunchKernelGGL(k_init_fields<double>, grid, blk, 0, stream, static_cast<double*>(dst), flags, rho, ux,
-                           uy, n, nx, ny, rho0, ax, ay);
+        hipLaunchKernelGGL(k_init_fields<double>, grid, blk, 0, stream, g, static_cast<double*>(pop),
+                           static_cast<double*>(link), rho, ux, uy, rho0, ax, ay);
     return hipGetLastError();
 }
 
-hipError_t launch_moments(bool fp32, const void* src, const uint8_t* flags, double* rho, double* ux, double* uy,
-                          uint32_t n, uint32_t nx, uint32_t ny, double rho0, double ax, double ay,
-                          hipStream_t stream)
+hipError_t launch_moments(bool fp32, const Geo& g, const void* pop, const void* link, double* rho, double* ux,
+                          double* uy, double rho0, double ax, double ay, hipStream_t stream)
 {
-    const dim3 grid(ceil_div(n, 256)), blk(256);
+    const dim3 grid(ceil_div(g.n, 256)), blk(256);
     if (fp32)
-        hipLaunchKernelGGL(k_moments<float>, grid, blk, 0, stream, static_cast<const float*>(src), flags, rho, ux, uy,
-                           n, nx, ny, rho0, ax, ay);
+        hipLaunchKernelGGL(k_moments<float>, grid, blk, 0, stream, g, static_cast<const float*>(pop),
+                           static_cast<const float*>(link), rho, ux, uy, rho0, ax, ay);
     else
-        hipLaunchKernelGGL(k_moments<double>, grid, blk, 0, stream, static_cast<const double*>(src), flags, rho, ux,
-                           uy, n, nx, ny, rho0, ax, ay);
+        hipLaunchKernelGGL(k_moments<double>, grid, blk, 0, stream, g, static_cast<const double*>(pop),
+                           static_cast<const double*>(link), rho, ux, uy, rho0, ax, ay);
     return hipGetLastError();
 }
 
@@ -581,7 +662,7 @@ uint32_t residual_blocks(uint32_t n)
 
 hipError_t launch_residual(bool fp32, const ReduceArgs& a, double* out, hipStream_t stream)
 {
-    const uint32_t nb = residual_blocks(a.n);
+    const uint32_t nb = residual_blocks(a.g.n);
     if (fp32)
         hipLaunchKernelGGL(k_residual_partial<float>, dim3(nb), dim3(kRedBlock), 0, stream, a);
     else

@@ -73,7 +73,7 @@ SIGNATURES = {
     "lbm_residual": (C.c_int32, [_VP, _DPTR, _DPTR]),
     "lbm_set_stream": (C.c_int32, [_VP, _VP]),
     "lbm_synchronize": (C.c_int32, [_VP]),
-    "lbm_set_launch": (C.c_int32, [_VP, C.c_int32, C.c_int32]),
+    "lbm_set_launch": (C.c_int32, [_VP, C.c_int32]),
     "lbm_set_timing": (C.c_int32, [_VP, C.c_int32]),
     "lbm_last_step_ms": (C.c_int32, [_VP, _DPTR, C.POINTER(C.c_int64)]),
 }
@@ -231,8 +231,8 @@ class Lattice:
     def synchronize(self):
         _check(self._lib.lbm_synchronize(self._h))
 
-    def set_launch(self, block=256, xcd_remap=False):
-        _check(self._lib.lbm_set_launch(self._h, int(block), int(bool(xcd_remap))))
+    def set_launch(self, block=256):
+        _check(self._lib.lbm_set_launch(self._h, int(block)))
 
     def set_timing(self, on=True):
         _check(self._lib.lbm_set_timing(self._h, int(bool(on))))

@@ -261,21 +261,19 @@ def test_device_parameter_error():
 
 
 def test_launch_shapes_bitwise():
-    """The launch shape (block size, XCD remap) does not change a single bit of the result."""
+    """The launch shape (block size) does not change a single bit of the result."""
     pb = _cylinders(256, 11)
-    ref = None
     for precision in ("fp64", "fp32"):
         ref = None
         for block in (64, 128, 256, 512, 1024):
-            for remap in (False, True):
-                lat = _lattice(pb, precision)
-                lat.set_launch(block, remap)
-                lat.init_fields(*_smooth_fields(pb["solid"].shape, 5))
-                lat.step(37)
-                out = np.stack(lat.moments_host())
-                if ref is None:
-                    ref = out
-                assert np.array_equal(out, ref), (precision, block, remap)
+            lat = _lattice(pb, precision)
+            lat.set_launch(block)
+            lat.init_fields(*_smooth_fields(pb["solid"].shape, 5))
+            lat.step(37)
+            out = np.stack(lat.moments_host())
+            if ref is None:
+                ref = out
+            assert np.array_equal(out, ref), (precision, block)
 
 
 def test_device_pointer_paths():
