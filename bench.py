@@ -13,8 +13,10 @@ beside it.  MLUPS counts lattice sites (solid included); MFLUPS counts fluid nod
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -77,6 +79,24 @@ def time_precision(problem, precision, steps, warmup, block):
     )
     lat.close()
     return out
+
+
+def counted_traffic(precision, n):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when the summary is for
+    another workload or the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{precision}_cylinders{n}.md")
+    src = os.path.join(ROOT, "paper_2012_14707_amd", "csrc", "lbm_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    if data.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return dict(read_bytes=data["read_bytes"], write_bytes=data["write_bytes"],
+                profiled_avg_ns=data["avg_duration_ns"], source=os.path.relpath(path, ROOT))
 
 
 def cpu_baseline(problem, steps=2):
@@ -172,8 +192,16 @@ def main():
             "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": None,
         },
+        "kernel_avg_ms": round(head["kernel_avg_ms"], 5),
+        "bytes_per_launch": head["bytes_per_step"],
         "mflups": round(head["mflups"], 1),
     }
+    counted = counted_traffic(head_name, args.n)
+    if counted:
+        total = counted["read_bytes"] + counted["write_bytes"]
+        line["roofline"]["traffic"] = round(total / (head["kernel_avg_ms"] * 1e-3) / 1e9, 1)
+        line["hbm_counters"] = {"read_bytes": round(counted["read_bytes"]), "write_bytes": round(counted["write_bytes"]),
+                                "source": counted["source"]}
     if "fp64" in results and head_name != "fp64":
         r = results["fp64"]
         line["fp64"] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
