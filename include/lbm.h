@@ -185,6 +185,80 @@ lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block);
 lbm_status lbm_set_timing(lbm_ctx *ctx, int32_t on);
 lbm_status lbm_last_step_ms(lbm_ctx *ctx, double *ms_total, int64_t *nsteps);
 
+/* ------------------------------------------------------------------------------------------
+ * Batches: many independent lattices of uneven sizes and parameters (e.g. a Kn / gamma /
+ * geometry sweep) advanced together by one persistent kernel launch per step, captured in HIP
+ * graphs.  All instances share the precision and the diffuse reading; everything else (size,
+ * mask, links, Kn, H, modes, relaxation times, force) is per instance.  Each instance computes
+ * exactly what a single lbm_ctx with the same inputs computes, bit for bit.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Per-instance state reported by lbm_batch_solve. */
+enum {
+    LBM_RUNNING = 0,
+    LBM_CONVERGED = 1, /* residual <= tol */
+    LBM_FLOOR = 2,     /* residual stopped decreasing (rounding floor of the storage precision) */
+    LBM_CAPPED = 3,    /* reached max_steps */
+    LBM_DIVERGED = 4   /* residual or mass not finite */
+};
+
+/* Launch shape of the batched step. */
+typedef struct {
+    int32_t block;         /* threads per block = sites per tile: 128, 256, 512 or 1024 */
+    int32_t graph_steps;   /* steps captured per HIP graph (even, >= 2) */
+    int32_t blocks_per_cu; /* persistent grid of (compute units x blocks_per_cu) blocks; 0 = one block per tile */
+    int32_t reserved;
+} lbm_batch_launch;
+
+/* Creates a batch of n_inst lattices.  params[i], solids[i], links[i] (n_links[i] records) are
+ * instance i's arguments of lbm_create, with the same validation; all params[i].precision and
+ * params[i].diffuse must be equal (else LBM_E_INVAL).  Inputs are copied.  All instances start at
+ * rest and active.  stream: hipStream_t for all work (NULL: the batch creates its own stream;
+ * graphs cannot be captured on the null stream). */
+lbm_status lbm_batch_create(int32_t n_inst, const lbm_params *params, const uint8_t *const *solids,
+                            const lbm_link *const *links, const int64_t *n_links, void *stream, lbm_batch **out);
+lbm_status lbm_batch_destroy(lbm_batch *b);
+
+/* Instance i's lbm_info (steps = steps taken by that instance). */
+lbm_status lbm_batch_info(const lbm_batch *b, int32_t inst, lbm_info *info);
+
+/* Rest state for every instance; all become active. */
+lbm_status lbm_batch_init_rest(lbm_batch *b);
+
+/* Advances every active instance by nsteps (graph replays plus eager launches for a remainder). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Marks instances active (nonzero) or retired (0); retired instances keep their state and are
+ * skipped by lbm_batch_step.  active: host [n_inst]. */
+lbm_status lbm_batch_set_active(lbm_batch *b, const uint8_t *active);
+
+/* Residual and mass (definitions of lbm_residual) of every active instance into residual[i],
+ * mass[i] (host, [n_inst]); retired instances report the values of their last check.
+ * Synchronises.  LBM_E_UNSTABLE if any active instance is not finite (values still written). */
+lbm_status lbm_batch_residuals(lbm_batch *b, double *residual, double *mass);
+
+/* rho, u of instance inst (layout and ownership of lbm_moments). */
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t inst, double *rho, double *ux, double *uy, int32_t device_ptrs);
+
+/* Runs every instance from its current state until it retires: every check_every steps (even)
+ * the residuals are computed and an instance stops as LBM_CONVERGED (residual <= tol),
+ * LBM_DIVERGED (not finite), LBM_CAPPED (steps >= max_steps) or LBM_FLOOR (residual above
+ * 0.995 x its value 50 checks earlier while below 1e-5).  Outputs (host, [n_inst], any may be
+ * NULL): status, steps taken by the instance, last residual. */
+lbm_status lbm_batch_solve(lbm_batch *b, double tol, int64_t check_every, int64_t max_steps, int32_t *status,
+                           int64_t *steps, double *residual);
+
+lbm_status lbm_batch_set_launch(lbm_batch *b, const lbm_batch_launch *launch);
+lbm_status lbm_batch_get_launch(const lbm_batch *b, lbm_batch_launch *launch);
+
+/* Autotuner: times trial_steps steps of every candidate launch shape (block 128/256/512,
+ * graph_steps 2/10/50, blocks_per_cu 0/2/4/8) on this batch with HIP events, keeps the fastest
+ * and records it in the text file cache_path (NULL: no cache) under a key of (GPU architecture,
+ * precision, total sites, instance count); a cached key is reused without timing.  The batch is
+ * reset to rest afterwards.  Every candidate computes identical results. */
+lbm_status lbm_batch_tune(lbm_batch *b, const char *cache_path, int32_t trial_steps, lbm_batch_launch *chosen);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,60 @@ struct StepArgs {
     T c_e, c_eps, c_q, c_s;    // 1 - s/2 (forcing weights)
 };
 
+// Physical constants of one lattice in the storage precision.
+template <typename T>
+struct Phys {
+    T rho0, ax, ay;
+    T s_e, s_eps, s_q, s_s;
+    T c_e, c_eps, c_q, c_s;
+};
+
+// One instance of a batch: its sites occupy [off, off + n) of the batch's site space (off is a
+// multiple of the largest tile), laid out as an nx x ny lattice.
+template <typename T>
+struct BatchInst {
+    uint32_t off, n, nx, ny;
+    Phys<T> ph;
+};
+
+// One tile of an active instance: `start` is the tile's first site, local to the instance.
+struct TileRef {
+    uint32_t inst, start;
+};
+
+// Arguments of the batched persistent step kernel.
+template <typename T>
+struct BatchArgs {
+    const uint8_t* flags;         // batch site space
+    const int32_t* chunk_base;    // per 64-site chunk of the batch site space; global link indices
+    Level<T> src, dst;            // planes over the batch site space (stride ps); link arrays global
+    LinkCoef<T> coef;             // global link indices
+    double* ux_out;               // batch site space
+    double* uy_out;
+    const BatchInst<T>* inst;
+    const TileRef* tiles;         // active tiles, instance by instance
+    const uint32_t* n_active;     // number of active tiles (device resident, read at launch)
+    uint32_t ps;                  // plane stride of the batch site space
+    uint32_t lds_links;           // link slots of the LDS staging area (max links of one tile)
+};
+
+// Batched residual: per active tile partial sums, then per active instance a fixed-order sum over
+// its tile range [tile_begin[i], tile_begin[i+1]) of the active list.
+template <typename T>
+struct BatchReduceArgs {
+    const uint8_t* flags;
+    const int32_t* chunk_base;
+    const T* pop;
+    const T* link;
+    const double* ux_prev;
+    const double* uy_prev;
+    const BatchInst<T>* inst;
+    const TileRef* tiles;
+    const uint32_t* n_active;
+    double* partial;              // 3 per active tile
+    uint32_t ps;
+};
+
 struct LinkInput {
     const double* q;
     const double* ubx;
@@ -73,6 +127,7 @@ struct PrecomputeArgs {
     double r_override, l_override;
     int32_t l_mode, r_mode, diffuse;
     int64_t n_links;
+    int64_t row_stride;  // elements between coefficient rows (>= n_links)
 };
 
 struct ReduceArgs {
@@ -94,6 +149,19 @@ hipError_t launch_step_f64(const StepArgs<double>& a, int block, bool write_u, b
                            hipStream_t stream);
 hipError_t launch_step_f32(const StepArgs<float>& a, int block, bool write_u, bool node_diffuse,
                            hipStream_t stream);
+// Batched persistent step over the active tile list with a grid of `grid` blocks of `block` threads.
+hipError_t launch_step_batch_f64(const BatchArgs<double>& a, int block, uint32_t grid, bool write_u,
+                                 bool node_diffuse, hipStream_t stream);
+hipError_t launch_step_batch_f32(const BatchArgs<float>& a, int block, uint32_t grid, bool write_u,
+                                 bool node_diffuse, hipStream_t stream);
+// Per-active-instance sums (|du|^2, |u|^2, sum drho) into out[3 * i] for the active instances
+// i = 0 .. n_inst_active-1, whose tiles are tile_begin[i] .. tile_begin[i+1]-1 of the active list.
+hipError_t launch_residual_batch_f64(const BatchReduceArgs<double>& a, int block, uint32_t grid,
+                                     const uint32_t* tile_begin, uint32_t n_inst_active, double* out,
+                                     hipStream_t stream);
+hipError_t launch_residual_batch_f32(const BatchReduceArgs<float>& a, int block, uint32_t grid,
+                                     const uint32_t* tile_begin, uint32_t n_inst_active, double* out,
+                                     hipStream_t stream);
 hipError_t launch_fill_zero(void* ptr, uint64_t bytes, hipStream_t stream);
 hipError_t launch_init_fields(bool fp32, const Geo& g, void* pop, void* link, const double* rho, const double* ux,
                               const double* uy, double rho0, double ax, double ay, hipStream_t stream);

@@ -180,14 +180,17 @@ struct LinkStage {
     T* dif;  // w_i (drho + rho phi_i(u)) in the node reading, w_i drho in the wall reading
 };
 
+// One tile of BLOCK consecutive sites starting at `start` (a multiple of BLOCK) of the lattice
+// described by a.g: collision and streaming of its fluid sites, then the boundary values of its
+// wall links.  Shared by the single-lattice kernel and the batched persistent kernel, so that both
+// compute bit-identical results.
 template <typename T, bool WRITE_U, bool NODE, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
+__device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, unsigned char* lds_raw)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
     const Geo& g = a.g;
-    const uint32_t s = blockIdx.x * BLOCK + threadIdx.x;
-    // link range of this block (uniform, scalar loads)
-    const uint32_t c0 = blockIdx.x * (BLOCK / kChunk);
+    const uint32_t s = start + threadIdx.x;
+    // link range of this tile (uniform, scalar loads)
+    const uint32_t c0 = start / kChunk;
     const uint32_t c1 = min(c0 + BLOCK / kChunk, g.nchunks);
     const uint32_t kblk = static_cast<uint32_t>(g.chunk_base[c0]);
     const uint32_t nl_blk = static_cast<uint32_t>(g.chunk_base[c1]) - kblk;
@@ -320,15 +323,68 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
         for (int i = 0; i < 9; ++i) dst[i * ps + s] = T(0);
     }
 
-    if (nl_blk == 0) return;  // block-uniform
-    __syncthreads();
-    // link-parallel phase: Eq. (EqNewBDSC) in deviation form,
-    //   g_i(x, t+1) = a1 g_ibar + a2 g'_i + a3 g'_ibar + beta rho + kappa w_i (drho + rho phi_i(u))
-    const LinkCoef<T> c = a.coef;
-    for (uint32_t j = threadIdx.x; j < nl_blk; j += BLOCK) {
-        const uint32_t k = kblk + j;
-        a.dst.link[k] = c.a1[k] * st.gb[j] + c.a2[k] * st.hi[j] + c.a3[k] * st.hb[j] + c.beta[k] * st.rho[j] +
-                        c.kappa[k] * st.dif[j];
+    if (nl_blk != 0) {  // block-uniform
+        __syncthreads();
+        // link-parallel phase: Eq. (EqNewBDSC) in deviation form,
+        //   g_i(x, t+1) = a1 g_ibar + a2 g'_i + a3 g'_ibar + beta rho + kappa w_i (drho + rho phi_i(u))
+        const LinkCoef<T> c = a.coef;
+        for (uint32_t j = threadIdx.x; j < nl_blk; j += BLOCK) {
+            const uint32_t k = kblk + j;
+            a.dst.link[k] = c.a1[k] * st.gb[j] + c.a2[k] * st.hi[j] + c.a3[k] * st.hb[j] +
+                            c.beta[k] * st.rho[j] + c.kappa[k] * st.dif[j];
+        }
+    }
+}
+
+template <typename T, bool WRITE_U, bool NODE, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    step_tile<T, WRITE_U, NODE, BLOCK>(a, blockIdx.x * BLOCK, lds_raw);
+}
+
+// View of instance `in` of a batch: its flags, chunk offsets and u record start at its site offset
+// in the batch's site space; its planes are the batch planes shifted by the offset (same stride);
+// link indices in the chunk table are global.
+template <typename T>
+__device__ __forceinline__ StepArgs<T> instance_args(const BatchArgs<T>& b, const BatchInst<T>& in)
+{
+    StepArgs<T> a;
+    a.g = Geo{b.flags + in.off, b.chunk_base + in.off / kChunk, in.n, in.nx, in.ny, (in.n + kChunk - 1) / kChunk,
+              b.ps};
+    a.src = Level<T>{b.src.pop + in.off, b.src.link};
+    a.dst = Level<T>{b.dst.pop + in.off, b.dst.link};
+    a.coef = b.coef;
+    a.ux_out = b.ux_out + in.off;
+    a.uy_out = b.uy_out + in.off;
+    a.lds_links = b.lds_links;
+    a.rho0 = in.ph.rho0;
+    a.ax = in.ph.ax;
+    a.ay = in.ph.ay;
+    a.s_e = in.ph.s_e;
+    a.s_eps = in.ph.s_eps;
+    a.s_q = in.ph.s_q;
+    a.s_s = in.ph.s_s;
+    a.c_e = in.ph.c_e;
+    a.c_eps = in.ph.c_eps;
+    a.c_q = in.ph.c_q;
+    a.c_s = in.ph.c_s;
+    return a;
+}
+
+// Persistent batched step: a fixed grid strides over the device-resident list of active tiles
+// (instance, local start); retiring an instance only shrinks that list, so a captured graph of
+// these launches stays valid.
+template <typename T, bool WRITE_U, bool NODE, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_step_batch(const BatchArgs<T> b)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint32_t ntile = *b.n_active;
+    for (uint32_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const TileRef tr = b.tiles[t];
+        const StepArgs<T> a = instance_args(b, b.inst[tr.inst]);
+        step_tile<T, WRITE_U, NODE, BLOCK>(a, tr.start, lds_raw);
+        __syncthreads();  // the next tile reuses the LDS staging area
     }
 }
 
@@ -344,7 +400,7 @@ __global__ void __launch_bounds__(256) k_precompute(const LinkInput in, const Pr
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= a.n_links) return;
-    const int64_t nl = a.n_links;
+    const int64_t nl = a.row_stride;
     const double g = in.q[k];
     const double ts = a.tau_s, L1 = a.L1, E = a.E, sq = a.sq6pi;
     const double t2 = 2.0 * ts - 1.0;
@@ -489,10 +545,11 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Block-level fixed-order sum of three values; result valid in thread 0.
+// Block-level fixed-order sum of three values over BLOCK threads; result valid in thread 0.
+template <int BLOCK = kRedBlock>
 __device__ __forceinline__ void block_sum3(double& a, double& b, double& c)
 {
-    __shared__ double sh[3][kRedBlock / 64];
+    __shared__ double sh[3][BLOCK / 64];
     a = wave_sum(a);
     b = wave_sum(b);
     c = wave_sum(c);
@@ -505,7 +562,7 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c)
     __syncthreads();
     if (threadIdx.x == 0) {
         a = b = c = 0.0;
-        for (int i = 0; i < kRedBlock / 64; ++i) {
+        for (int i = 0; i < BLOCK / 64; ++i) {
             a += sh[0][i];
             b += sh[1][i];
             c += sh[2][i];
@@ -559,6 +616,60 @@ __global__ void __launch_bounds__(kRedBlock) k_residual_final(const double* part
     }
 }
 
+// Batched residual partials: one active tile per loop trip, sums in a fixed order per tile.
+template <typename T, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_residual_batch_partial(const BatchReduceArgs<T> a)
+{
+    const uint32_t ntile = *a.n_active;
+    for (uint32_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const TileRef tr = a.tiles[t];
+        const BatchInst<T> in = a.inst[tr.inst];
+        const Geo g{a.flags + in.off, a.chunk_base + in.off / kChunk, in.n, in.nx, in.ny,
+                    (in.n + kChunk - 1) / kChunk, a.ps};
+        const uint32_t s = tr.start + threadIdx.x;
+        const SiteLinks sl = site_links(g, s);
+        double s_du = 0.0, s_u = 0.0, s_dr = 0.0;
+        if (sl.fl != kSolid) {
+            const Nbr b = neighbours(s, g.nx, g.ny);
+            const Pop<T> p = pull(a.pop + in.off, a.link, g.ps, s, b, sl.fl, sl.k0);
+            double dr, r, u, v;
+            macro_fp64(p, static_cast<double>(in.ph.rho0), static_cast<double>(in.ph.ax),
+                       static_cast<double>(in.ph.ay), dr, r, u, v);
+            const double du = u - a.ux_prev[in.off + s], dv = v - a.uy_prev[in.off + s];
+            s_du = du * du + dv * dv;
+            s_u = u * u + v * v;
+            s_dr = dr;
+        }
+        block_sum3<BLOCK>(s_du, s_u, s_dr);
+        if (threadIdx.x == 0) {
+            a.partial[3 * t + 0] = s_du;
+            a.partial[3 * t + 1] = s_u;
+            a.partial[3 * t + 2] = s_dr;
+        }
+        __syncthreads();
+    }
+}
+
+// One block per active instance: fixed-order sum over its tiles.
+__global__ void __launch_bounds__(kRedBlock) k_residual_batch_final(const double* partial, const uint32_t* tile_begin,
+                                                                    double* out)
+{
+    const uint32_t i = blockIdx.x;
+    const uint32_t t0 = tile_begin[i], t1 = tile_begin[i + 1];
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += kRedBlock) {
+        x += partial[3 * t + 0];
+        y += partial[3 * t + 1];
+        z += partial[3 * t + 2];
+    }
+    block_sum3(x, y, z);
+    if (threadIdx.x == 0) {
+        out[3 * i + 0] = x;
+        out[3 * i + 1] = y;
+        out[3 * i + 2] = z;
+    }
+}
+
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
 
 template <typename T, int BLOCK>
@@ -592,7 +703,77 @@ hipError_t launch_step_t(const StepArgs<T>& a, int block, bool write_u, bool nod
     }
 }
 
+template <typename T, int BLOCK>
+hipError_t launch_batch_block(const BatchArgs<T>& a, uint32_t grid, bool write_u, bool node, hipStream_t stream)
+{
+    const size_t lds = 5 * sizeof(T) * a.lds_links;
+    if (write_u) {
+        if (node)
+            hipLaunchKernelGGL((k_step_batch<T, true, true, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
+        else
+            hipLaunchKernelGGL((k_step_batch<T, true, false, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
+    } else {
+        if (node)
+            hipLaunchKernelGGL((k_step_batch<T, false, true, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
+        else
+            hipLaunchKernelGGL((k_step_batch<T, false, false, BLOCK>), dim3(grid), dim3(BLOCK), lds, stream, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_t(const BatchArgs<T>& a, int block, uint32_t grid, bool write_u, bool node,
+                          hipStream_t stream)
+{
+    switch (block) {
+    case 128: return launch_batch_block<T, 128>(a, grid, write_u, node, stream);
+    case 512: return launch_batch_block<T, 512>(a, grid, write_u, node, stream);
+    case 1024: return launch_batch_block<T, 1024>(a, grid, write_u, node, stream);
+    default: return launch_batch_block<T, 256>(a, grid, write_u, node, stream);
+    }
+}
+
+template <typename T>
+hipError_t launch_residual_batch_t(const BatchReduceArgs<T>& a, int block, uint32_t grid,
+                                   const uint32_t* tile_begin, uint32_t n_inst, double* out, hipStream_t stream)
+{
+    switch (block) {
+    case 128: hipLaunchKernelGGL((k_residual_batch_partial<T, 128>), dim3(grid), dim3(128), 0, stream, a); break;
+    case 512: hipLaunchKernelGGL((k_residual_batch_partial<T, 512>), dim3(grid), dim3(512), 0, stream, a); break;
+    case 1024: hipLaunchKernelGGL((k_residual_batch_partial<T, 1024>), dim3(grid), dim3(1024), 0, stream, a); break;
+    default: hipLaunchKernelGGL((k_residual_batch_partial<T, 256>), dim3(grid), dim3(256), 0, stream, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_inst == 0) return e;
+    hipLaunchKernelGGL(k_residual_batch_final, dim3(n_inst), dim3(kRedBlock), 0, stream, a.partial, tile_begin, out);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_step_batch_f64(const BatchArgs<double>& a, int block, uint32_t grid, bool write_u, bool node,
+                                 hipStream_t stream)
+{
+    return launch_batch_t<double>(a, block, grid, write_u, node, stream);
+}
+
+hipError_t launch_step_batch_f32(const BatchArgs<float>& a, int block, uint32_t grid, bool write_u, bool node,
+                                 hipStream_t stream)
+{
+    return launch_batch_t<float>(a, block, grid, write_u, node, stream);
+}
+
+hipError_t launch_residual_batch_f64(const BatchReduceArgs<double>& a, int block, uint32_t grid,
+                                     const uint32_t* tile_begin, uint32_t n_inst, double* out, hipStream_t stream)
+{
+    return launch_residual_batch_t<double>(a, block, grid, tile_begin, n_inst, out, stream);
+}
+
+hipError_t launch_residual_batch_f32(const BatchReduceArgs<float>& a, int block, uint32_t grid,
+                                     const uint32_t* tile_begin, uint32_t n_inst, double* out, hipStream_t stream)
+{
+    return launch_residual_batch_t<float>(a, block, grid, tile_begin, n_inst, out, stream);
+}
 
 size_t step_lds_bytes(bool fp32, uint32_t max_links) { return 5 * (fp32 ? 4 : 8) * size_t(max_links); }
 

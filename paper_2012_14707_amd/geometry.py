@@ -246,3 +246,29 @@ def counts(problem):
     """(fluid nodes, sites, links) of a problem."""
     s = problem["solid"]
     return int((s == 0).sum()), int(s.size), int(len(problem["links"]["x"]))
+
+
+def batched_sweep_config4(seed=1, n_poiseuille=128, n_couette=128, u_target=1e-3):
+    """Uneven-instance sweep: slip Poiseuille channels (fluid rows ~ U{16..512}, 4 periodic columns,
+    gamma ~ U[0.05, 0.95]) and cylindrical Couette annuli (outer radius ~ U[16, 128] lu, radius ratio
+    0.5, grid 2 R2 + 4 with the centre at the grid centre, inner wall speed 0.01), Kn log-uniform in
+    [1e-3, 0.1].  The channel force is set per instance so that the centre-line speed of the
+    no-slip parabola, a H^2 / (8 nu), is u_target (low Mach at every H and Kn)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sq6pi = math.sqrt(6.0 / math.pi)
+    out = []
+    for _ in range(n_poiseuille):
+        rows = int(rng.integers(16, 513))
+        gamma = float(rng.uniform(0.05, 0.95))
+        kn = float(10 ** rng.uniform(-3, -1))
+        h = (rows - 1) + 2 * gamma
+        nu = sq6pi * kn * h / 3.0        # (tau_s - 1/2)/3 with tau_s from Eq. (tKnrela)
+        a = 8.0 * nu * u_target / (h * h)
+        out.append(channel(rows, nx=4, gamma=gamma, kn=kn, ax=a))
+    for _ in range(n_couette):
+        r2 = float(rng.uniform(16.0, 128.0))
+        kn = float(10 ** rng.uniform(-3, -1))
+        n = int(math.ceil(2 * r2)) + 4
+        c = (n - 1) / 2.0
+        out.append(annulus(n, 0.5 * r2, r2, (c, c), u_inner=0.01, u_outer=0.0, kn=kn))
+    return out

@@ -55,6 +55,13 @@ class Info(C.Structure):
                 ("reserved", C.c_int32), ("bytes_per_step", C.c_int64), ("steps", C.c_int64)]
 
 
+class BatchLaunch(C.Structure):
+    _fields_ = [("block", C.c_int32), ("graph_steps", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+BATCH_STATUS = {0: "running", 1: "converged", 2: "floor", 3: "capped", 4: "diverged"}
+
 # Every entry point of include/lbm.h with its ctypes signature.
 _VP = C.c_void_p
 _DPTR = C.POINTER(C.c_double)
@@ -76,6 +83,19 @@ SIGNATURES = {
     "lbm_set_launch": (C.c_int32, [_VP, C.c_int32]),
     "lbm_set_timing": (C.c_int32, [_VP, C.c_int32]),
     "lbm_last_step_ms": (C.c_int32, [_VP, _DPTR, C.POINTER(C.c_int64)]),
+    "lbm_batch_create": (C.c_int32, [C.c_int32, C.POINTER(Params), C.POINTER(_VP), C.POINTER(_VP),
+                                     C.POINTER(C.c_int64), _VP, C.POINTER(_VP)]),
+    "lbm_batch_destroy": (C.c_int32, [_VP]),
+    "lbm_batch_info": (C.c_int32, [_VP, C.c_int32, C.POINTER(Info)]),
+    "lbm_batch_init_rest": (C.c_int32, [_VP]),
+    "lbm_batch_step": (C.c_int32, [_VP, C.c_int64]),
+    "lbm_batch_set_active": (C.c_int32, [_VP, _VP]),
+    "lbm_batch_residuals": (C.c_int32, [_VP, _VP, _VP]),
+    "lbm_batch_moments": (C.c_int32, [_VP, C.c_int32, _VP, _VP, _VP, C.c_int32]),
+    "lbm_batch_solve": (C.c_int32, [_VP, C.c_double, C.c_int64, C.c_int64, _VP, _VP, _VP]),
+    "lbm_batch_set_launch": (C.c_int32, [_VP, C.POINTER(BatchLaunch)]),
+    "lbm_batch_get_launch": (C.c_int32, [_VP, C.POINTER(BatchLaunch)]),
+    "lbm_batch_tune": (C.c_int32, [_VP, C.c_char_p, C.c_int32, C.POINTER(BatchLaunch)]),
 }
 
 _lib = None
@@ -252,3 +272,97 @@ class Lattice:
             if res <= tol:
                 break
         return steps, res
+
+
+class Batch:
+    """Many lattices of uneven size advanced together (lbm_batch_* of include/lbm.h)."""
+
+    def __init__(self, problems, precision="fp32", stream=None):
+        lib = load()
+        self._lib = lib
+        n = len(problems)
+        self.shapes = []
+        params = (Params * n)()
+        solids = (C.c_void_p * n)()
+        links = (C.c_void_p * n)()
+        counts = (C.c_int64 * n)()
+        self._keep = []
+        for i, pb in enumerate(problems):
+            solid = np.ascontiguousarray(pb["solid"], dtype=np.uint8)
+            self.shapes.append(solid.shape)
+            params[i] = make_params(pb["params"], solid.shape, precision)
+            arr, nl = make_links(pb["links"])
+            self._keep += [solid, arr]
+            solids[i] = solid.ctypes.data
+            links[i] = C.cast(arr, C.c_void_p).value
+            counts[i] = nl
+        h = C.c_void_p()
+        strm = None if stream is False else _stream_handle(stream)
+        _check(lib.lbm_batch_create(n, params, solids, links, counts, strm, C.byref(h)))
+        self._h = h
+        self.n = n
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, i):
+        inf = Info()
+        _check(self._lib.lbm_batch_info(self._h, int(i), C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in Info._fields_}
+
+    def init_rest(self):
+        _check(self._lib.lbm_batch_init_rest(self._h))
+
+    def step(self, n=1):
+        _check(self._lib.lbm_batch_step(self._h, int(n)))
+
+    def set_active(self, active):
+        a = np.ascontiguousarray(np.asarray(active, dtype=bool).astype(np.uint8))
+        _check(self._lib.lbm_batch_set_active(self._h, a.ctypes.data_as(C.c_void_p)))
+
+    def residuals(self, raise_unstable=True):
+        r = np.zeros(self.n)
+        m = np.zeros(self.n)
+        st = self._lib.lbm_batch_residuals(self._h, r.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p))
+        if st != 0 and (raise_unstable or st != -6):
+            _check(st)
+        return r, m
+
+    def moments_host(self, i):
+        a = [np.zeros(self.shapes[i]) for _ in range(3)]
+        _check(self._lib.lbm_batch_moments(self._h, int(i), *[x.ctypes.data_as(C.c_void_p) for x in a], 0))
+        return a
+
+    def solve(self, tol, check_every=100, max_steps=1_000_000):
+        """Runs every instance until it retires; returns (status names, steps, residuals)."""
+        st = np.zeros(self.n, np.int32)
+        steps = np.zeros(self.n, np.int64)
+        res = np.zeros(self.n)
+        _check(self._lib.lbm_batch_solve(self._h, float(tol), int(check_every), int(max_steps),
+                                         st.ctypes.data_as(C.c_void_p), steps.ctypes.data_as(C.c_void_p),
+                                         res.ctypes.data_as(C.c_void_p)))
+        return [BATCH_STATUS[int(x)] for x in st], steps, res
+
+    def set_launch(self, block=256, graph_steps=10, blocks_per_cu=4):
+        lb = BatchLaunch(int(block), int(graph_steps), int(blocks_per_cu), 0)
+        _check(self._lib.lbm_batch_set_launch(self._h, C.byref(lb)))
+
+    def get_launch(self):
+        lb = BatchLaunch()
+        _check(self._lib.lbm_batch_get_launch(self._h, C.byref(lb)))
+        return dict(block=lb.block, graph_steps=lb.graph_steps, blocks_per_cu=lb.blocks_per_cu)
+
+    def tune(self, cache_path=None, trial_steps=100):
+        lb = BatchLaunch()
+        path = cache_path.encode() if cache_path else None
+        _check(self._lib.lbm_batch_tune(self._h, path, int(trial_steps), C.byref(lb)))
+        return dict(block=lb.block, graph_steps=lb.graph_steps, blocks_per_cu=lb.blocks_per_cu)

@@ -37,7 +37,8 @@ def test_struct_layouts(tmp_path):
     """The ctypes mirrors have the size and field offsets the C compiler gives the header's structs."""
     src = tmp_path / "layout.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
-    for cname, py in (("lbm_link", lbm.Link), ("lbm_params", lbm.Params), ("lbm_info", lbm.Info)):
+    for cname, py in (("lbm_link", lbm.Link), ("lbm_params", lbm.Params), ("lbm_info", lbm.Info),
+                      ("lbm_batch_launch", lbm.BatchLaunch)):
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
@@ -47,7 +48,8 @@ def test_struct_layouts(tmp_path):
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                        check=True).stdout.splitlines())
-    for cname, py in (("lbm_link", lbm.Link), ("lbm_params", lbm.Params), ("lbm_info", lbm.Info)):
+    for cname, py in (("lbm_link", lbm.Link), ("lbm_params", lbm.Params), ("lbm_info", lbm.Info),
+                      ("lbm_batch_launch", lbm.BatchLaunch)):
         assert int(out[cname]) == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
@@ -139,3 +141,36 @@ def test_null_and_size_errors():
     assert lib.lbm_destroy(None) == 0
     assert lib.lbm_step(None, 1) == -1
     assert lib.lbm_get_info(None, None) == -1
+
+
+def test_batch_validation_errors():
+    """Batch creation validates every instance on the host and names the failing one."""
+    lib = lbm.load()
+    good = G.poiseuille_config1()
+    bad = _mutate(G.poiseuille_config1(), lambda pb: pb["links"]["q"].__setitem__(0, 2.0))
+
+    def create(problems, precisions):
+        n = len(problems)
+        params = (lbm.Params * n)()
+        solids = (C.c_void_p * n)()
+        links = (C.c_void_p * n)()
+        counts = (C.c_int64 * n)()
+        keep = []
+        for i, (pb, prec) in enumerate(zip(problems, precisions)):
+            s = np.ascontiguousarray(pb["solid"], np.uint8)
+            params[i] = lbm.make_params(pb["params"], s.shape, prec)
+            arr, nl = lbm.make_links(pb["links"])
+            keep += [s, arr]
+            solids[i] = s.ctypes.data
+            links[i] = C.cast(arr, C.c_void_p).value
+            counts[i] = nl
+        h = C.c_void_p()
+        st = lib.lbm_batch_create(n, params, solids, links, counts, None, C.byref(h))
+        return st, h, lib.lbm_last_error().decode()
+
+    st, h, msg = create([good, good], ["fp32", "fp64"])
+    assert st == -1 and not h.value and "precision" in msg
+    st, h, msg = create([good, bad], ["fp32", "fp32"])
+    assert st == -4 and not h.value and msg.startswith("instance 1")
+    assert lib.lbm_batch_destroy(None) == 0
+    assert lib.lbm_batch_step(None, 1) == -1
