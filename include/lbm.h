@@ -259,6 +259,118 @@ lbm_status lbm_batch_get_launch(const lbm_batch *b, lbm_batch_launch *launch);
  * reset to rest afterwards.  Every candidate computes identical results. */
 lbm_status lbm_batch_tune(lbm_batch *b, const char *cache_path, int32_t trial_steps, lbm_batch_launch *chosen);
 
+/* ------------------------------------------------------------------------------------------
+ * Learned warm start.  A convolutional encoder-decoder predicts an initial (u, rho) from the
+ * problem statement (mask, distance ratios, Kn, force direction); the lattice then starts from
+ * f^eq(rho, u) (lbm_init_fields) instead of rest.  The network is not part of the paper: it only
+ * changes the initial state, and the converged field is the lattice's own.
+ *
+ * Tensors are NHWC: element (image n, row y, column x, channel c) of a [n, h, w, C] tensor is at
+ * ((n * h + y) * w + x) * C + c.  bf16 tensors (IEEE-754 binary32 with the low 16 bits dropped,
+ * round to nearest even) must be 16-byte aligned and have a multiple of 8 channels.  Every
+ * pointer below is device memory unless it says host.  Calls are asynchronous on `stream`
+ * (hipStream_t, NULL = null stream) unless they return a host value.
+ * ------------------------------------------------------------------------------------------ */
+
+/* 'Same' convolution, ksize 1 or 3, on the matrix cores with fp32 accumulation:
+ *   out[n,y,x,co] = act(bias[co] + sum_{ky,kx,ci} in[n, y+ky-k/2, x+kx-k/2, ci] w[ky*k+kx][co][ci])
+ * where in[] outside the image is 0 (periodic = 0) or wraps around (periodic = 1: row y + h and
+ * column x + w are row y and column x).  in bf16 [n,h,w,cin]; w bf16 [k*k][cout][cin]; bias fp32
+ * [cout] or NULL; act = max(., 0) if relu.  out bf16 [n,h,w,cout] and/or out32 fp32
+ * [n,h,w,cout] (either may be NULL). */
+lbm_status lbm_conv2d_forward(const void *in, const void *w, const float *bias, void *out, float *out32,
+                              int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize,
+                              int32_t relu, int32_t periodic, void *stream);
+
+/* Input gradient of lbm_conv2d_forward without activation:
+ *   din[n,y,x,ci] = sum_{ky,kx,co} dout[n, y-ky+k/2, x-kx+k/2, co] w[ky*k+kx][co][ci]
+ * (indices outside the image as in lbm_conv2d_forward with the same periodic flag)
+ * dout bf16 [n,h,w,cout] -> din bf16 [n,h,w,cin].  wt: bf16 workspace of k*k*cin*cout elements
+ * (overwritten with the flipped, transposed kernel). */
+lbm_status lbm_conv2d_dgrad(const void *dout, const void *w, void *din, void *wt, int32_t n, int32_t h, int32_t wd,
+                            int32_t cin, int32_t cout, int32_t ksize, int32_t periodic, void *stream);
+
+/* Weight and bias gradients of lbm_conv2d_forward without activation:
+ *   dw[ky*k+kx][co][ci] = sum_{n,y,x} dout[n,y,x,co] in[n, y+ky-k/2, x+kx-k/2, ci],  db[co] = sum dout[.., co]
+ * fp32 outputs (db may be NULL), deterministic (fixed reduction order).  work: fp32 workspace of
+ * at least *elems elements as returned by lbm_conv2d_wgrad_workspace for the same sizes (host). */
+lbm_status lbm_conv2d_wgrad_workspace(int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize,
+                                      int64_t *elems);
+lbm_status lbm_conv2d_wgrad(const void *in, const void *dout, float *dw, float *db, float *work, int64_t work_elems,
+                            int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize,
+                            int32_t periodic, void *stream);
+
+/* Network shape: level l (0 .. levels-1) works at (height >> l) x (width >> l) with
+ * base_channels << l channels and two 3x3 convolutions + ReLU; levels are joined by 2x2 average
+ * pooling on the way down and nearest 2x upsampling + concatenation with the same level's encoder
+ * output on the way up; a 1x1 convolution gives out_channels outputs.  The input tensor has
+ * in_channels rounded up to a multiple of 8 (the extra channels are zero). */
+typedef struct {
+    int32_t levels;        /* 1 .. 8 */
+    int32_t base_channels; /* multiple of 8 */
+    int32_t in_channels;   /* >= 1 */
+    int32_t out_channels;  /* 1 .. 8 */
+    int32_t height, width; /* multiples of 2^(levels-1) */
+    int32_t max_batch;     /* images per forward/backward call */
+    int32_t periodic;      /* 0: convolutions zero-pad the image edges; 1: they wrap around (doubly
+                              periodic domains) */
+} lbm_nn_config;
+
+typedef struct lbm_nn lbm_nn;
+
+/* Allocates the network (fp32 master parameters, Adam moments, bf16 copies, activations for
+ * max_batch images) on the current device; parameters get a seeded He-normal initialisation and
+ * zero biases.  Every call on the network runs on `stream` (hipStream_t, NULL = null stream).
+ * Parameter vector layout, in this order: for each encoder level 0..levels-1 its two
+ * convolutions, then for each decoder level levels-2..0 its two convolutions, then the 1x1 output
+ * convolution; each convolution is its weights [k*k][cout][cin] followed by its bias [cout]; the
+ * output convolution has cout = 8 (rows >= out_channels stay zero). */
+lbm_status lbm_nn_create(const lbm_nn_config *cfg, uint64_t seed, void *stream, lbm_nn **out);
+lbm_status lbm_nn_destroy(lbm_nn *net);
+lbm_status lbm_nn_param_count(const lbm_nn *net, int64_t *count);
+/* Host fp32 parameter vector in / out (set also resets the Adam state). */
+lbm_status lbm_nn_set_params(lbm_nn *net, const float *host);
+lbm_status lbm_nn_get_params(const lbm_nn *net, float *host);
+/* Host fp32 gradient of the last lbm_nn_backward, parameter layout. */
+lbm_status lbm_nn_get_grads(const lbm_nn *net, float *host);
+
+/* Forward pass of `batch` images: in bf16 [batch, height, width, ceil8(in_channels)];
+ * out fp32 [batch, height, width, out_channels] (NULL: kept inside for lbm_nn_backward). */
+lbm_status lbm_nn_forward(lbm_nn *net, const void *in, float *out, int32_t batch);
+
+/* Loss and gradients of the last forward pass (same batch):
+ *   loss = sum_{p: mask[p] != 0, c < out_channels} (out[p,c] - target[p,c])^2 / (count * out_channels)
+ * with count = number of nonzero mask pixels; target fp32 [batch, height, width, out_channels],
+ * mask uint8 [batch, height, width].  Writes every parameter gradient; *loss (host) on return.
+ * Synchronises the stream. */
+lbm_status lbm_nn_backward(lbm_nn *net, const float *target, const uint8_t *mask, int32_t batch, double *loss);
+
+/* One Adam step on every parameter from the last gradients (bias-corrected, step count kept by
+ * the network), then refreshes the bf16 copies. */
+lbm_status lbm_nn_adam_step(lbm_nn *net, float lr, float beta1, float beta2, float eps);
+
+/* Input features of one lattice (the network's 12 inputs, channels 12 .. channels-1 zero):
+ *   0      1 on fluid sites, 0 on solid sites
+ *   1..8   on fluid sites: q of the wall link in D2Q9 direction d (1 = E, 2 = N, 3 = W, 4 = S,
+ *          5 = NE, 6 = NW, 7 = SW, 8 = SE), 1 where direction d has no wall link; 0 on solid sites
+ *   9      kn_feature, 10 ax_feature, 11 ay_feature (constant over the image)
+ * solid uint8 [ny * nx] (nonzero = solid); links: n_links records of lbm_link in device memory,
+ * records outside the grid or with dir outside 1..8 are skipped (duplicates: one of them is kept).
+ * out bf16 [ny, nx, channels], channels a multiple of 8 and >= 16. */
+lbm_status lbm_nn_features(const uint8_t *solid, const lbm_link *links, int64_t n_links, int32_t nx, int32_t ny,
+                           float kn_feature, float ax_feature, float ay_feature, void *out, int32_t channels,
+                           void *stream);
+
+/* Initial fields from one image of network output pred fp32 [ny * nx, stride] (channels: u_x, u_y,
+ * delta rho, normalised): on fluid sites ux = u_scale pred0, uy = u_scale pred1,
+ * rho = rho0 + rho_scale (pred2 - mean of pred2 over fluid sites), so that the total mass equals
+ * that of the rest state; solid sites get rho0 and 0.  rho, ux, uy: fp64 [ny * nx].  *n_bad (host)
+ * = number of fluid sites with a non-finite prediction (the caller falls back to rest if > 0).
+ * Synchronises the stream. */
+lbm_status lbm_nn_fields(const float *pred, int32_t stride, const uint8_t *solid, int32_t nx, int32_t ny,
+                         double u_scale, double rho_scale, double rho0, double *rho, double *ux, double *uy,
+                         int64_t *n_bad, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

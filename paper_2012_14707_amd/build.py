@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIB_DIR, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_host.hip", "lbm_kernels.hip"]
+SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_host.hip", "lbm_kernels.hip", "lbm_nn.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,1074 @@
+// Learned warm start: a convolutional encoder-decoder that maps the problem statement (mask,
+// distance ratios, Kn, force direction) to an initial (u, rho) for the lattice solver, trained on
+// steady fields that the solver computes.  Hand-written for gfx950: convolutions are implicit GEMMs
+// on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) with fp32 accumulation; activations are
+// NHWC bf16; master weights, gradients and Adam state are fp32.
+//
+// Network (levels L, base channels C): encoder level l has C 2^l channels and two 3x3
+// convolutions with ReLU; levels are joined by 2x2 average pooling.  Decoder level l (L-2 .. 0)
+// upsamples the level below (nearest), concatenates the encoder output of level l, and applies two
+// 3x3 convolutions with ReLU.  A 1x1 convolution gives the outputs.  The encoder output of level l
+// is written straight into the second channel slice of decoder level l's concatenation buffer, so
+// the skip connection costs no copy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_host.hpp"
+#include "lbm_internal.hpp"
+
+using lbm::DeviceGuard;
+using lbm::fail;
+using lbm::ignore;
+
+namespace lbm {
+namespace nn {
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f4;
+
+// ------------------------------------------------------------------------ matrix-core GEMMs
+
+constexpr int TM = 64, TN = 64, TK = 32, LDK = 40;  // LDS rows padded to 40 bf16 (80 bytes)
+
+// A channel slice of an NHWC bf16 tensor: element (pixel p, channel c) at p * cs + co + c.
+struct Slice {
+    bf16* p;
+    int cs, co;
+};
+struct CSlice {
+    const bf16* p;
+    int cs, co;
+};
+
+struct ConvArgs {
+    CSlice x;           // input, Cin channels
+    const bf16* w;      // [taps][Cout][Cin], Cin contiguous
+    const float* bias;  // [Cout] or null
+    Slice y;            // bf16 output (y.p null: none)
+    float* yf;          // fp32 output [pixels][Cout] (null: none)
+    int N, H, W, Cin, Cout, relu;
+    int periodic;       // 1: rows and columns wrap around; 0: zero padding
+};
+
+__device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, int& x)
+{
+    n = p / (H * W);
+    const int r = p - n * H * W;
+    y = r / W;
+    x = r - y * W;
+}
+
+// out[p][co] = act(bias[co] + sum_{tap, ci} x[p + off(tap)][ci] w[tap][co][ci]), with zero padding
+// or periodic wrap-around at the image edges.
+// One block computes a 64-pixel x 64-channel tile; each of its four waves a 32 x 32 quarter with
+// four 16x16x32 MFMAs per 32-deep K step.  K runs over (tap, ci); Cin is a multiple of 8 so every
+// 8-wide K group lies in one tap and is one 16-byte load.
+template <int TAPS>
+__global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
+{
+    __shared__ __align__(16) bf16 As[TM * LDK];
+    __shared__ __align__(16) bf16 Bs[TN * LDK];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int P = a.N * a.H * a.W;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int K = TAPS * a.Cin;
+    const int lm = tid / 4, lg = tid % 4;  // tile row loaded by this thread, 8-wide K group
+    const int p = m0 + lm;
+    int pn = 0, py = 0, px = 0;
+    if (p < P) decompose(p, a.H, a.W, pn, py, px);
+    const int co_l = n0 + lm;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        const int k = k0 + lg * 8;
+        bf16x8 va = {}, vb = {};
+        if (k < K) {
+            const int tap = k / a.Cin, ci = k - tap * a.Cin;
+            if (p < P) {
+                int yy = py + (TAPS == 9 ? tap / 3 - 1 : 0), xx = px + (TAPS == 9 ? tap % 3 - 1 : 0);
+                if (a.periodic) {
+                    yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+                    xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+                }
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    va = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((pn * a.H + yy) * a.W + xx) * a.x.cs +
+                                                          a.x.co + ci);
+            }
+            if (co_l < a.Cout)
+                vb = *reinterpret_cast<const bf16x8*>(a.w + (size_t(tap) * a.Cout + co_l) * a.Cin + ci);
+        }
+        *reinterpret_cast<bf16x8*>(As + lm * LDK + lg * 8) = va;
+        *reinterpret_cast<bf16x8*>(Bs + lm * LDK + lg * 8) = vb;
+        __syncthreads();
+        // A operand: lane holds row lane % 16, k = 8 (lane / 16) .. +7; B likewise by column
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + lane % 16) * LDK + 8 * (lane / 16));
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 fb =
+                    *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + lane % 16) * LDK + 8 * (lane / 16));
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // result: lane holds column lane % 16, rows 4 (lane / 16) + r
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + wn + 16 * j + lane % 16;
+            if (col >= a.Cout) continue;
+            const float b = a.bias ? a.bias[col] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + 16 * i + 4 * (lane / 16) + r;
+                if (row >= P) continue;
+                float v = acc[i][j][r] + b;
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.y.p) a.y.p[size_t(row) * a.y.cs + a.y.co + col] = bf16(v);
+                if (a.yf) a.yf[size_t(row) * a.Cout + col] = v;
+            }
+        }
+}
+
+struct WgradArgs {
+    CSlice x;        // layer input, Cin channels
+    CSlice dz;       // output gradient, Cout channels
+    float* partial;  // [nsplit][taps][Cout][Cin]
+    int N, H, W, Cin, Cout, chunk;  // chunk: pixels per split (multiple of TK)
+    int periodic;
+};
+
+// partial[s][tap][co][ci] = sum over the pixels p of split s of dz[p][co] x[p + off(tap)][ci].
+// GEMM with M = Cout, N = Cin, K = pixels; both operands are staged through LDS transposed to
+// K-contiguous rows.  Grid (Cout / 64, Cin / 64, taps * nsplit).
+template <int TAPS>
+__global__ void __launch_bounds__(256) k_conv_wgrad(const WgradArgs a)
+{
+    __shared__ __align__(16) bf16 As[TM * LDK];
+    __shared__ __align__(16) bf16 Bs[TN * LDK];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int P = a.N * a.H * a.W;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int tap = blockIdx.z % TAPS, split = blockIdx.z / TAPS;
+    const int dy = (TAPS == 9 ? tap / 3 - 1 : 0), dx = (TAPS == 9 ? tap % 3 - 1 : 0);
+    const int pbeg = split * a.chunk, pend = min(P, pbeg + a.chunk);
+    const int lp = tid / 8, lc = (tid % 8) * 8;  // pixel of the K tile, 8-channel group
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
+    for (int k0 = pbeg; k0 < pend; k0 += TK) {
+        const int p = k0 + lp;
+        bf16x8 va = {}, vb = {};
+        if (p < pend) {
+            if (m0 + lc < a.Cout)
+                va = *reinterpret_cast<const bf16x8*>(a.dz.p + size_t(p) * a.dz.cs + a.dz.co + m0 + lc);
+            int pn, py, px;
+            decompose(p, a.H, a.W, pn, py, px);
+            int yy = py + dy, xx = px + dx;
+            if (a.periodic) {
+                yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+            }
+            if (n0 + lc < a.Cin && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                vb = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((pn * a.H + yy) * a.W + xx) * a.x.cs + a.x.co +
+                                                      n0 + lc);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            As[(lc + e) * LDK + lp] = va[e];
+            Bs[(lc + e) * LDK + lp] = vb[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + lane % 16) * LDK + 8 * (lane / 16));
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 fb =
+                    *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + lane % 16) * LDK + 8 * (lane / 16));
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    float* out = a.partial + (size_t(split) * TAPS + tap) * size_t(a.Cout) * a.Cin;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + wn + 16 * j + lane % 16;  // ci
+            if (col >= a.Cin) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + 16 * i + 4 * (lane / 16) + r;  // co
+                if (row < a.Cout) out[size_t(row) * a.Cin + col] = acc[i][j][r];
+            }
+        }
+}
+
+// grad[e] = sum_s partial[s][e], in split order (deterministic).
+__global__ void __launch_bounds__(256) k_sum_splits(const float* partial, int nsplit, size_t n, float* grad)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += partial[size_t(k) * n + e];
+    grad[e] = s;
+}
+
+// Bias gradient partials: part[b][co] = sum of dz[p][co] over pixel block b (256 pixels).
+__global__ void __launch_bounds__(256) k_bias_partial(CSlice dz, int P, int Cout, float* part)
+{
+    const int pb = blockIdx.x;
+    const int p1 = min(P, (pb + 1) * 256);
+    for (int co = threadIdx.x; co < Cout; co += 256) {
+        float s = 0.f;
+        for (int p = pb * 256; p < p1; ++p) s += float(dz.p[size_t(p) * dz.cs + dz.co + co]);
+        part[size_t(pb) * Cout + co] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bias_reduce(const float* part, int nb, int Cout, float* grad)
+{
+    const int co = blockIdx.x * 256 + threadIdx.x;
+    if (co >= Cout) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[size_t(b) * Cout + co];
+    grad[co] = s;
+}
+
+// Kernel for the input gradient: wt[tap][ci][co] = w[taps - 1 - tap][co][ci] (mirrored taps,
+// channel roles exchanged), so the input gradient is a forward convolution of dz with wt.
+template <typename T>
+__global__ void __launch_bounds__(256) k_flip(const T* w, bf16* wt, int taps, int Cout, int Cin)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= size_t(taps) * Cout * Cin) return;
+    const int co = int(e % Cout);
+    const size_t q = e / Cout;
+    const int ci = int(q % Cin), tap = int(q / Cin);
+    wt[e] = bf16(float(w[(size_t(taps - 1 - tap) * Cout + co) * Cin + ci]));
+}
+
+// ------------------------------------------------------------------------ elementwise kernels
+
+// dz[p][c] = g[p][c] if y[p][c] > 0 else 0 (ReLU backward; dz contiguous with C channels)
+__global__ void __launch_bounds__(256) k_relu_bwd(CSlice g, CSlice y, bf16* dz, int P, int C)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= size_t(P) * C) return;
+    const size_t p = e / C, c = e - p * C;
+    const float yv = float(y.p[p * y.cs + y.co + c]);
+    dz[e] = yv > 0.f ? g.p[p * g.cs + g.co + c] : bf16(0.f);
+}
+
+// 2x2 average pooling: out (H/2 x W/2) from in (H x W)
+__global__ void __launch_bounds__(256) k_pool_fwd(CSlice in, Slice out, int N, int H, int W, int C)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= size_t(N) * Ho * Wo * C) return;
+    const int c = int(e % C);
+    const size_t q = e / C;
+    const int x = int(q % Wo), y = int((q / Wo) % Ho), n = int(q / (size_t(Wo) * Ho));
+    float s = 0.f;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+            s += float(in.p[size_t((n * H + 2 * y + dy) * W + 2 * x + dx) * in.cs + in.co + c]);
+    out.p[q * out.cs + out.co + c] = bf16(0.25f * s);
+}
+
+// gin[2y+dy][2x+dx][c] += gout[y][x][c] / 4   (gin at H x W)
+__global__ void __launch_bounds__(256) k_pool_bwd_add(CSlice gout, Slice gin, int N, int H, int W, int C)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= size_t(N) * H * W * C) return;
+    const int c = int(e % C);
+    const size_t q = e / C;
+    const int x = int(q % W), y = int((q / W) % H), n = int(q / (size_t(W) * H));
+    const float g = 0.25f * float(gout.p[size_t((n * (H / 2) + y / 2) * (W / 2) + x / 2) * gout.cs + gout.co + c]);
+    bf16& t = gin.p[q * gin.cs + gin.co + c];
+    t = bf16(float(t) + g);
+}
+
+// nearest 2x upsampling: out (2H x 2W) from in (H x W)
+__global__ void __launch_bounds__(256) k_up_fwd(CSlice in, Slice out, int N, int H, int W, int C)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    const int H2 = 2 * H, W2 = 2 * W;
+    if (e >= size_t(N) * H2 * W2 * C) return;
+    const int c = int(e % C);
+    const size_t q = e / C;
+    const int x = int(q % W2), y = int((q / W2) % H2), n = int(q / (size_t(W2) * H2));
+    out.p[q * out.cs + out.co + c] = in.p[size_t((n * H + y / 2) * W + x / 2) * in.cs + in.co + c];
+}
+
+// gin[y][x][c] = sum of the four gout values it was copied to (gin at H x W)
+__global__ void __launch_bounds__(256) k_up_bwd(CSlice gout, Slice gin, int N, int H, int W, int C)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= size_t(N) * H * W * C) return;
+    const int c = int(e % C);
+    const size_t q = e / C;
+    const int x = int(q % W), y = int((q / W) % H), n = int(q / (size_t(W) * H));
+    float s = 0.f;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+            s += float(gout.p[size_t((n * 2 * H + 2 * y + dy) * 2 * W + 2 * x + dx) * gout.cs + gout.co + c]);
+    gin.p[q * gin.cs + gin.co + c] = bf16(s);
+}
+
+// Fluid pixel count of the mask, per 256-pixel block.
+__global__ void __launch_bounds__(256) k_mask_count(const uint8_t* mask, int P, float* part)
+{
+    __shared__ float sh[256];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    sh[threadIdx.x] = (p < P && mask[p]) ? 1.f : 0.f;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// out[0] = sum of part[0 .. n) in fp64, fixed order.
+__global__ void __launch_bounds__(256) k_sum_partials(const float* part, int n, double* out)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Masked squared error over the first `used` of C output channels: per-block sums of
+// mask (y - t)^2 into part, and dz = 2 mask (y - t) / (count used) into the bf16 gradient.
+__global__ void __launch_bounds__(256) k_mse(const float* y, const float* t, const uint8_t* mask, int P, int C,
+                                             int used, const double* count, bf16* dz, float* part)
+{
+    __shared__ float sh[256];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const float inv = float(1.0 / (fmax(count[0], 1.0) * used));
+    float s = 0.f;
+    if (p < P) {
+        const bool m = mask[p] != 0;
+        for (int c = 0; c < C; ++c) {
+            float g = 0.f;
+            if (m && c < used) {
+                const float d = y[size_t(p) * C + c] - t[size_t(p) * used + c];
+                s += d * d;
+                g = 2.f * d * inv;
+            }
+            dz[size_t(p) * C + c] = bf16(g);
+        }
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Adam on fp32 master parameters, then the bf16 copy used by the forward pass.
+__global__ void __launch_bounds__(256) k_adam(float* w, float* m, float* v, const float* g, bf16* wb, size_t n,
+                                              float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float gr = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gr;
+    const float vv = b2 * v[e] + (1.f - b2) * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    const float ww = w[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    w[e] = ww;
+    wb[e] = bf16(ww);
+}
+
+__global__ void __launch_bounds__(256) k_to_bf16(const float* w, bf16* wb, size_t n)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e < n) wb[e] = bf16(w[e]);
+}
+
+// -------------------------------------------------------------- features and initial fields
+
+__global__ void __launch_bounds__(256) k_feat_sites(const uint8_t* solid, int n, float f_kn, float f_ax, float f_ay,
+                                                    bf16* x, int C)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const float fl = solid[s] ? 0.f : 1.f;
+    bf16* o = x + size_t(s) * C;
+    for (int c = 0; c < C; ++c) {
+        float v = 0.f;
+        if (c <= 8) v = fl;
+        else if (c == 9) v = f_kn;
+        else if (c == 10) v = f_ax;
+        else if (c == 11) v = f_ay;
+        o[c] = bf16(v);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_feat_links(const lbm_link* links, int64_t nl, const uint8_t* solid, int nx,
+                                                    int ny, bf16* x, int C)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= nl) return;
+    const lbm_link l = links[i];
+    if (l.x < 0 || l.x >= nx || l.y < 0 || l.y >= ny || l.dir < 1 || l.dir > 8) return;
+    const size_t s = size_t(l.y) * nx + l.x;
+    if (solid[s]) return;
+    x[s * C + l.dir] = bf16(float(l.q));
+}
+
+// One block: mean of the predicted density deviation over fluid sites (fp64, fixed order), then
+// the fields.  bad[0] = fluid sites with a non-finite prediction.
+__global__ void __launch_bounds__(1024) k_fields(const float* pred, int stride, const uint8_t* solid, int n, double us,
+                                                 double rs, double rho0, double* rho, double* ux, double* uy,
+                                                 long long* bad)
+{
+    __shared__ double s_sum[1024];
+    __shared__ int s_cnt[1024], s_bad[1024];
+    const int t = threadIdx.x;
+    double sum = 0.0;
+    int cnt = 0, nb = 0;
+    for (int s = t; s < n; s += 1024) {
+        if (solid[s]) continue;
+        const float a = pred[size_t(s) * stride], b = pred[size_t(s) * stride + 1], c = pred[size_t(s) * stride + 2];
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c)) {
+            ++nb;
+        } else {
+            sum += c;
+            ++cnt;
+        }
+    }
+    s_sum[t] = sum;
+    s_cnt[t] = cnt;
+    s_bad[t] = nb;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) {
+            s_sum[t] += s_sum[t + w];
+            s_cnt[t] += s_cnt[t + w];
+            s_bad[t] += s_bad[t + w];
+        }
+        __syncthreads();
+    }
+    const double mean = s_cnt[0] ? s_sum[0] / s_cnt[0] : 0.0;
+    for (int s = t; s < n; s += 1024) {
+        if (solid[s]) {
+            rho[s] = rho0;
+            ux[s] = 0.0;
+            uy[s] = 0.0;
+        } else {
+            rho[s] = rho0 + rs * (double(pred[size_t(s) * stride + 2]) - mean);
+            ux[s] = us * double(pred[size_t(s) * stride]);
+            uy[s] = us * double(pred[size_t(s) * stride + 1]);
+        }
+    }
+    if (t == 0) bad[0] = s_bad[0];
+}
+
+inline unsigned blocks(size_t n) { return unsigned((n + 255) / 256); }
+
+// ------------------------------------------------------------------------------- launchers
+
+hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
+                        int Cout, int taps, bool relu, bool periodic, hipStream_t st)
+{
+    ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0};
+    const int P = N * H * W;
+    const dim3 grid((P + TM - 1) / TM, (Cout + TN - 1) / TN);
+    if (taps == 9)
+        hipLaunchKernelGGL(k_conv_fwd<9>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t flip(const T* w, bf16* wt, int taps, int Cout, int Cin, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flip<T>, dim3(blocks(size_t(taps) * Cout * Cin)), dim3(256), 0, st, w, wt, taps, Cout, Cin);
+    return hipGetLastError();
+}
+
+// Input gradient from the flipped kernel wt ([taps][Cin][Cout]): a forward convolution with the
+// channel roles exchanged (the adjoint of a zero-padded or of a periodic convolution is the
+// convolution with the mirrored kernel under the same edge rule).
+hipError_t conv_dgrad(CSlice dz, const bf16* wt, Slice dx, int N, int H, int W, int Cin, int Cout, int taps,
+                      bool periodic, hipStream_t st)
+{
+    return conv_forward(dz, wt, nullptr, dx, nullptr, N, H, W, Cout, Cin, taps, false, periodic, st);
+}
+
+struct WgradPlan {
+    int nsplit, chunk, nb;
+    size_t per, elems;
+};
+
+// Split of the pixel range: enough (tap, tile, split) blocks to fill the chip (about 1024), at
+// least 256 pixels per split.  elems = workspace (split partials + bias partials).
+WgradPlan wgrad_plan(int P, int Cin, int Cout, int taps)
+{
+    WgradPlan w{};
+    const int tiles = taps * ((Cout + TM - 1) / TM) * ((Cin + TN - 1) / TN);
+    const int target = std::max(1, std::min(1024 / tiles, P / 256));
+    w.chunk = ((P + target - 1) / target + TK - 1) / TK * TK;
+    w.nsplit = std::max(1, (P + w.chunk - 1) / w.chunk);
+    w.nb = (P + 255) / 256;
+    w.per = size_t(taps) * Cout * Cin;
+    w.elems = size_t(target) * w.per + size_t(w.nb) * Cout;
+    return w;
+}
+
+hipError_t conv_wgrad(CSlice x, CSlice dz, float* dw, float* db, float* work, int N, int H, int W, int Cin, int Cout,
+                      int taps, bool periodic, hipStream_t st)
+{
+    const int P = N * H * W;
+    const WgradPlan pl = wgrad_plan(P, Cin, Cout, taps);
+    WgradArgs a{x, dz, work, N, H, W, Cin, Cout, pl.chunk, periodic ? 1 : 0};
+    const dim3 grid((Cout + TM - 1) / TM, (Cin + TN - 1) / TN, taps * pl.nsplit);
+    if (taps == 9)
+        hipLaunchKernelGGL(k_conv_wgrad<9>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(pl.per)), dim3(256), 0, st, work, pl.nsplit, pl.per, dw);
+    if (db) {
+        float* bpart = work + size_t(pl.nsplit) * pl.per;
+        hipLaunchKernelGGL(k_bias_partial, dim3(pl.nb), dim3(256), 0, st, dz, P, Cout, bpart);
+        hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(size_t(Cout))), dim3(256), 0, st, bpart, pl.nb, Cout, db);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace lbm
+
+// ================================================================================ network
+
+namespace {
+
+using lbm::nn::bf16;
+using lbm::nn::CSlice;
+using lbm::nn::Slice;
+
+struct Conv {
+    int taps = 0, cin = 0, cout = 0, level = 0;
+    size_t w_off = 0, b_off = 0;  // offsets into the flat fp32 parameter vector
+    bf16* w = nullptr;            // bf16 weights [taps][cout][cin]
+    bf16* wt = nullptr;           // flipped weights [taps][cin][cout] for the input gradient
+};
+
+// One resolution level; activations and their gradients are bf16 NHWC for max_batch images.
+struct Level {
+    int H = 0, W = 0, C = 0, cin = 0;
+    Conv c1, c2;  // encoder
+    Conv d1, d2;  // decoder (levels above the bottleneck)
+    bf16 *in = nullptr, *e1 = nullptr, *cat = nullptr, *e2 = nullptr, *d1o = nullptr, *d2o = nullptr;
+    bf16 *g_in = nullptr, *g_e1 = nullptr, *g_cat = nullptr, *g_e2 = nullptr, *g_d1o = nullptr, *g_d2o = nullptr;
+};
+
+constexpr int kOutPad = 8;  // output channels of the last convolution (rows beyond out_channels stay 0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+struct lbm_nn {
+    lbm_nn_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Level> lv;
+    Conv out;
+    std::vector<Conv*> convs;
+    size_t n_params = 0;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // fp32 master, gradient, Adam moments
+    bf16* wb = nullptr;                                            // bf16 copy of every parameter
+    bf16* wt_all = nullptr;                                        // flipped bf16 kernels
+    bf16* dz = nullptr;       // pre-activation gradient of the convolution being differentiated
+    float* work = nullptr;    // weight-gradient workspace
+    float* part = nullptr;    // loss / count partials
+    float* yout = nullptr;    // last forward output, fp32 [P][kOutPad]
+    bf16* g_out = nullptr;    // its gradient
+    double* d_red = nullptr;  // [0] fluid count, [1] loss sum
+    double* h_red = nullptr;  // pinned host copy
+    int last_n = 0;
+    int64_t adam_t = 0;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+int chan(const lbm_nn* n, int l) { return n->cfg.base_channels << l; }
+
+void nn_release(lbm_nn* n)
+{
+    if (!n) return;
+    {
+        DeviceGuard g(n->device);
+        ignore(hipStreamSynchronize(n->stream));
+        for (void* p : n->allocs) ignore(hipFree(p));
+        if (n->h_red) ignore(hipHostFree(n->h_red));
+    }
+    delete n;
+}
+
+template <typename T>
+bool nn_alloc(lbm_nn* n, T** p, size_t elems)
+{
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(elems, 1) * sizeof(T)) != hipSuccess) return false;
+    n->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return true;
+}
+
+CSlice cs(const bf16* p, int c, int off = 0) { return CSlice{p, c, off}; }
+Slice sl(bf16* p, int c, int off = 0) { return Slice{p, c, off}; }
+
+hipError_t fwd(lbm_nn* n, const Conv& c, CSlice x, Slice y, float* yf, int N, int H, int W, bool relu)
+{
+    return lbm::nn::conv_forward(x, c.w, n->w + c.b_off, y, yf, N, H, W, c.cin, c.cout, c.taps, relu,
+                                 n->cfg.periodic != 0, n->stream);
+}
+
+hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, int W)
+{
+    return lbm::nn::conv_wgrad(x, dz, n->g + c.w_off, n->g + c.b_off, n->work, N, H, W, c.cin, c.cout, c.taps,
+                               n->cfg.periodic != 0, n->stream);
+}
+
+// Backward of one convolution + ReLU.  g: gradient w.r.t. its output y (after ReLU), x: its
+// input.  Writes its weight and bias gradients and, if gx.p, the gradient w.r.t. x.
+hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g, Slice gx, int N, int H, int W)
+{
+    const int P = N * H * W;
+    hipLaunchKernelGGL(lbm::nn::k_relu_bwd, dim3(lbm::nn::blocks(size_t(P) * c.cout)), dim3(256), 0, n->stream, g, y,
+                       n->dz, P, c.cout);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const CSlice dz = cs(n->dz, c.cout);
+    e = wgrad(n, c, x, dz, N, H, W);
+    if (e != hipSuccess || !gx.p) return e;
+    return lbm::nn::conv_dgrad(dz, c.wt, gx, N, H, W, c.cin, c.cout, c.taps, n->cfg.periodic != 0, n->stream);
+}
+
+hipError_t refresh_flipped(lbm_nn* n)
+{
+    for (Conv* cv : n->convs) {
+        hipError_t e = lbm::nn::flip(n->w + cv->w_off, cv->wt, cv->taps, cv->cout, cv->cin, n->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+bool conv_sizes_ok(int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize)
+{
+    return n >= 1 && h >= 1 && wd >= 1 && cin >= 8 && cin % 8 == 0 && cin <= 65536 && cout >= 8 && cout % 8 == 0 &&
+           cout <= 65536 && (ksize == 1 || ksize == 3) && int64_t(n) * h * wd <= INT32_MAX / 2;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_conv2d_forward(const void* in, const void* w, const float* bias, void* out, float* out32, int32_t n,
+                              int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize, int32_t relu,
+                              int32_t periodic, void* stream)
+{
+    if (!in || !w || (!out && !out32)) return fail(LBM_E_INVAL, "null argument");
+    if (!conv_sizes_ok(n, h, wd, cin, cout, ksize)) return fail(LBM_E_INVAL, "convolution sizes out of range");
+    if (!aligned16(in) || !aligned16(w) || (out && !aligned16(out)))
+        return fail(LBM_E_INVAL, "bf16 tensors need 16-byte alignment");
+    LBM_HIP_TRY(lbm::nn::conv_forward(cs(static_cast<const bf16*>(in), cin), static_cast<const bf16*>(w), bias,
+                                      sl(static_cast<bf16*>(out), cout), out32, n, h, wd, cin, cout, ksize * ksize,
+                                      relu != 0, periodic != 0, static_cast<hipStream_t>(stream)));
+    return LBM_OK;
+}
+
+lbm_status lbm_conv2d_dgrad(const void* dout, const void* w, void* din, void* wt, int32_t n, int32_t h, int32_t wd,
+                            int32_t cin, int32_t cout, int32_t ksize, int32_t periodic, void* stream)
+{
+    if (!dout || !w || !din || !wt) return fail(LBM_E_INVAL, "null argument");
+    if (!conv_sizes_ok(n, h, wd, cin, cout, ksize)) return fail(LBM_E_INVAL, "convolution sizes out of range");
+    if (!aligned16(dout) || !aligned16(din) || !aligned16(wt)) return fail(LBM_E_INVAL, "bf16 tensors need 16-byte alignment");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int taps = ksize * ksize;
+    LBM_HIP_TRY(lbm::nn::flip(static_cast<const bf16*>(w), static_cast<bf16*>(wt), taps, cout, cin, st));
+    LBM_HIP_TRY(lbm::nn::conv_dgrad(cs(static_cast<const bf16*>(dout), cout), static_cast<const bf16*>(wt),
+                                    sl(static_cast<bf16*>(din), cin), n, h, wd, cin, cout, taps, periodic != 0, st));
+    return LBM_OK;
+}
+
+lbm_status lbm_conv2d_wgrad_workspace(int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize,
+                                      int64_t* elems)
+{
+    if (!elems) return fail(LBM_E_INVAL, "null argument");
+    if (!conv_sizes_ok(n, h, wd, cin, cout, ksize)) return fail(LBM_E_INVAL, "convolution sizes out of range");
+    *elems = int64_t(lbm::nn::wgrad_plan(n * h * wd, cin, cout, ksize * ksize).elems);
+    return LBM_OK;
+}
+
+lbm_status lbm_conv2d_wgrad(const void* in, const void* dout, float* dw, float* db, float* work, int64_t work_elems,
+                            int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize, int32_t periodic,
+                            void* stream)
+{
+    if (!in || !dout || !dw || !work) return fail(LBM_E_INVAL, "null argument");
+    int64_t need = 0;
+    const lbm_status s = lbm_conv2d_wgrad_workspace(n, h, wd, cin, cout, ksize, &need);
+    if (s != LBM_OK) return s;
+    if (work_elems < need)
+        return fail(LBM_E_INVAL, "workspace too small (%lld < %lld)", (long long)work_elems, (long long)need);
+    if (!aligned16(in) || !aligned16(dout)) return fail(LBM_E_INVAL, "bf16 tensors need 16-byte alignment");
+    LBM_HIP_TRY(lbm::nn::conv_wgrad(cs(static_cast<const bf16*>(in), cin), cs(static_cast<const bf16*>(dout), cout),
+                                    dw, db, work, n, h, wd, cin, cout, ksize * ksize, periodic != 0,
+                                    static_cast<hipStream_t>(stream)));
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_create(const lbm_nn_config* cfg, uint64_t seed, void* stream, lbm_nn** out)
+{
+    if (!out || !cfg) return fail(LBM_E_INVAL, "null argument");
+    *out = nullptr;
+    const lbm_nn_config c = *cfg;
+    if (c.levels < 1 || c.levels > 8 || c.base_channels < 8 || c.base_channels % 8 || c.in_channels < 1 ||
+        c.in_channels > 4096 || c.out_channels < 1 || c.out_channels > kOutPad || c.max_batch < 1 || c.height < 1 ||
+        c.width < 1 || (int64_t(c.base_channels) << (c.levels - 1)) > 8192)
+        return fail(LBM_E_INVAL, "network configuration out of range");
+    if (c.height % (1 << (c.levels - 1)) || c.width % (1 << (c.levels - 1)))
+        return fail(LBM_E_INVAL, "height and width must be multiples of 2^(levels-1)");
+    if (c.periodic != 0 && c.periodic != 1) return fail(LBM_E_INVAL, "periodic must be 0 or 1");
+    if (int64_t(c.max_batch) * c.height * c.width > INT32_MAX / 8)
+        return fail(LBM_E_INVAL, "max_batch * height * width too large");
+    lbm_nn* n = new lbm_nn();
+    n->cfg = c;
+    n->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&n->device) != hipSuccess) {
+        delete n;
+        return fail(LBM_E_HIP, "no HIP device available");
+    }
+    const int L = c.levels;
+    n->lv.resize(size_t(L));
+    size_t off = 0;
+    auto add = [&](Conv& cv, int taps, int cin, int cout, int level) {
+        cv.taps = taps;
+        cv.cin = cin;
+        cv.cout = cout;
+        cv.level = level;
+        cv.w_off = off;
+        off += size_t(taps) * cin * cout;
+        cv.b_off = off;
+        off += size_t(cout);
+        n->convs.push_back(&cv);
+    };
+    for (int l = 0; l < L; ++l) {
+        Level& v = n->lv[l];
+        v.H = c.height >> l;
+        v.W = c.width >> l;
+        v.C = chan(n, l);
+        v.cin = l == 0 ? (c.in_channels + 7) / 8 * 8 : chan(n, l - 1);
+        add(v.c1, 9, v.cin, v.C, l);
+        add(v.c2, 9, v.C, v.C, l);
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        Level& v = n->lv[l];
+        add(v.d1, 9, chan(n, l + 1) + v.C, v.C, l);
+        add(v.d2, 9, v.C, v.C, l);
+    }
+    add(n->out, 1, chan(n, 0), kOutPad, 0);
+    n->n_params = off;
+    const size_t B = size_t(c.max_batch);
+    bool ok = nn_alloc(n, &n->w, off) && nn_alloc(n, &n->g, off) && nn_alloc(n, &n->m, off) &&
+              nn_alloc(n, &n->v, off) && nn_alloc(n, &n->wb, off) && nn_alloc(n, &n->wt_all, off);
+    size_t max_act = 0, work = 0;
+    for (int l = 0; l < L && ok; ++l) {
+        Level& v = n->lv[l];
+        const size_t px = B * v.H * v.W;
+        const int ccat = l < L - 1 ? chan(n, l + 1) + v.C : 0;
+        max_act = std::max(max_act, px * size_t(v.C));
+        ok = nn_alloc(n, &v.in, px * v.cin) && nn_alloc(n, &v.e1, px * v.C) && nn_alloc(n, &v.g_in, px * v.cin) &&
+             nn_alloc(n, &v.g_e1, px * v.C);
+        if (ok && l < L - 1)
+            ok = nn_alloc(n, &v.cat, px * ccat) && nn_alloc(n, &v.g_cat, px * ccat) && nn_alloc(n, &v.d1o, px * v.C) &&
+                 nn_alloc(n, &v.g_d1o, px * v.C) && nn_alloc(n, &v.d2o, px * v.C) && nn_alloc(n, &v.g_d2o, px * v.C);
+        if (ok && l == L - 1) ok = nn_alloc(n, &v.e2, px * v.C) && nn_alloc(n, &v.g_e2, px * v.C);
+    }
+    for (const Conv* cv : n->convs) {
+        const int P = int(B) * n->lv[cv->level].H * n->lv[cv->level].W;
+        work = std::max(work, lbm::nn::wgrad_plan(P, cv->cin, cv->cout, cv->taps).elems);
+    }
+    const size_t px0 = B * c.height * c.width;
+    ok = ok && nn_alloc(n, &n->dz, max_act) && nn_alloc(n, &n->work, work) && nn_alloc(n, &n->part, px0 / 256 + 1) &&
+         nn_alloc(n, &n->yout, px0 * kOutPad) && nn_alloc(n, &n->g_out, px0 * kOutPad) && nn_alloc(n, &n->d_red, 2) &&
+         hipHostMalloc(reinterpret_cast<void**>(&n->h_red), 2 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        nn_release(n);
+        return fail(LBM_E_NOMEM, "network allocation failed");
+    }
+    for (Conv* cv : n->convs) {
+        cv->w = n->wb + cv->w_off;
+        cv->wt = n->wt_all + cv->w_off;
+    }
+    // seeded He-normal weights, zero biases; padded input and output channels start (and stay) 0
+    std::vector<float> hp(off, 0.f);
+    std::mt19937_64 rng(seed);
+    for (const Conv* cv : n->convs) {
+        std::normal_distribution<float> nd(0.f, std::sqrt(2.f / float(cv->taps * cv->cin)));
+        for (int t = 0; t < cv->taps; ++t)
+            for (int co = 0; co < cv->cout; ++co)
+                for (int ci = 0; ci < cv->cin; ++ci) {
+                    const float val = nd(rng);
+                    const bool dead =
+                        (cv == &n->out && co >= c.out_channels) || (cv == &n->lv[0].c1 && ci >= c.in_channels);
+                    hp[cv->w_off + (size_t(t) * cv->cout + co) * cv->cin + ci] = dead ? 0.f : val;
+                }
+    }
+    const lbm_status st = lbm_nn_set_params(n, hp.data());
+    if (st != LBM_OK) {
+        nn_release(n);
+        return st;
+    }
+    *out = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_destroy(lbm_nn* n)
+{
+    nn_release(n);
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_param_count(const lbm_nn* n, int64_t* count)
+{
+    if (!n || !count) return fail(LBM_E_INVAL, "null argument");
+    *count = int64_t(n->n_params);
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_set_params(lbm_nn* n, const float* host)
+{
+    if (!n || !host) return fail(LBM_E_INVAL, "null argument");
+    DeviceGuard g(n->device);
+    LBM_HIP_TRY(hipMemcpyAsync(n->w, host, sizeof(float) * n->n_params, hipMemcpyHostToDevice, n->stream));
+    LBM_HIP_TRY(lbm::launch_fill_zero(n->m, sizeof(float) * n->n_params, n->stream));
+    LBM_HIP_TRY(lbm::launch_fill_zero(n->v, sizeof(float) * n->n_params, n->stream));
+    LBM_HIP_TRY(lbm::launch_fill_zero(n->g, sizeof(float) * n->n_params, n->stream));
+    hipLaunchKernelGGL(lbm::nn::k_to_bf16, dim3(lbm::nn::blocks(n->n_params)), dim3(256), 0, n->stream, n->w, n->wb,
+                       n->n_params);
+    LBM_HIP_TRY(hipGetLastError());
+    LBM_HIP_TRY(refresh_flipped(n));
+    LBM_HIP_TRY(hipStreamSynchronize(n->stream));
+    n->adam_t = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_get_params(const lbm_nn* n, float* host)
+{
+    if (!n || !host) return fail(LBM_E_INVAL, "null argument");
+    DeviceGuard g(n->device);
+    LBM_HIP_TRY(hipMemcpyAsync(host, n->w, sizeof(float) * n->n_params, hipMemcpyDeviceToHost, n->stream));
+    LBM_HIP_TRY(hipStreamSynchronize(n->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_get_grads(const lbm_nn* n, float* host)
+{
+    if (!n || !host) return fail(LBM_E_INVAL, "null argument");
+    DeviceGuard g(n->device);
+    LBM_HIP_TRY(hipMemcpyAsync(host, n->g, sizeof(float) * n->n_params, hipMemcpyDeviceToHost, n->stream));
+    LBM_HIP_TRY(hipStreamSynchronize(n->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_forward(lbm_nn* n, const void* x, float* y, int32_t batch)
+{
+    if (!n || !x) return fail(LBM_E_INVAL, "null argument");
+    if (batch < 1 || batch > n->cfg.max_batch) return fail(LBM_E_INVAL, "batch outside 1 .. max_batch");
+    if (!aligned16(x)) return fail(LBM_E_INVAL, "input needs 16-byte alignment");
+    DeviceGuard g(n->device);
+    const int L = n->cfg.levels, N = batch;
+    Level& v0 = n->lv[0];
+    LBM_HIP_TRY(hipMemcpyAsync(v0.in, x, sizeof(bf16) * size_t(N) * v0.H * v0.W * v0.cin, hipMemcpyDeviceToDevice,
+                               n->stream));
+    for (int l = 0; l < L; ++l) {  // encoder
+        Level& v = n->lv[l];
+        LBM_HIP_TRY(fwd(n, v.c1, cs(v.in, v.cin), sl(v.e1, v.C), nullptr, N, v.H, v.W, true));
+        const Slice skip = l < L - 1 ? sl(v.cat, chan(n, l + 1) + v.C, chan(n, l + 1)) : sl(v.e2, v.C);
+        LBM_HIP_TRY(fwd(n, v.c2, cs(v.e1, v.C), skip, nullptr, N, v.H, v.W, true));
+        if (l < L - 1) {
+            Level& nx = n->lv[l + 1];
+            hipLaunchKernelGGL(lbm::nn::k_pool_fwd, dim3(lbm::nn::blocks(size_t(N) * nx.H * nx.W * v.C)), dim3(256), 0,
+                               n->stream, CSlice{skip.p, skip.cs, skip.co}, sl(nx.in, v.C), N, v.H, v.W, v.C);
+            LBM_HIP_TRY(hipGetLastError());
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {  // decoder
+        Level& v = n->lv[l];
+        const Level& below = n->lv[l + 1];
+        const int cup = chan(n, l + 1), ccat = cup + v.C;
+        const CSlice src = l == L - 2 ? cs(below.e2, below.C) : cs(below.d2o, below.C);
+        hipLaunchKernelGGL(lbm::nn::k_up_fwd, dim3(lbm::nn::blocks(size_t(N) * v.H * v.W * cup)), dim3(256), 0,
+                           n->stream, src, sl(v.cat, ccat, 0), N, below.H, below.W, cup);
+        LBM_HIP_TRY(hipGetLastError());
+        LBM_HIP_TRY(fwd(n, v.d1, cs(v.cat, ccat), sl(v.d1o, v.C), nullptr, N, v.H, v.W, true));
+        LBM_HIP_TRY(fwd(n, v.d2, cs(v.d1o, v.C), sl(v.d2o, v.C), nullptr, N, v.H, v.W, true));
+    }
+    const CSlice top = L == 1 ? cs(v0.e2, v0.C) : cs(v0.d2o, v0.C);
+    LBM_HIP_TRY(fwd(n, n->out, top, Slice{nullptr, 0, 0}, n->yout, N, v0.H, v0.W, false));
+    n->last_n = N;
+    if (y) {
+        const int oc = n->cfg.out_channels;
+        LBM_HIP_TRY(hipMemcpy2DAsync(y, sizeof(float) * oc, n->yout, sizeof(float) * kOutPad, sizeof(float) * oc,
+                                     size_t(N) * v0.H * v0.W, hipMemcpyDeviceToDevice, n->stream));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_backward(lbm_nn* n, const float* target, const uint8_t* mask, int32_t batch, double* loss)
+{
+    if (!n || !target || !mask) return fail(LBM_E_INVAL, "null argument");
+    if (batch != n->last_n || batch < 1) return fail(LBM_E_STATE, "backward needs the batch of the last forward");
+    DeviceGuard g(n->device);
+    const int L = n->cfg.levels, N = batch;
+    Level& v0 = n->lv[0];
+    const int P0 = N * v0.H * v0.W, oc = n->cfg.out_channels, nb = (P0 + 255) / 256;
+    // loss over fluid pixels and the gradient of the output
+    hipLaunchKernelGGL(lbm::nn::k_mask_count, dim3(nb), dim3(256), 0, n->stream, mask, P0, n->part);
+    hipLaunchKernelGGL(lbm::nn::k_sum_partials, dim3(1), dim3(256), 0, n->stream, n->part, nb, n->d_red);
+    hipLaunchKernelGGL(lbm::nn::k_mse, dim3(nb), dim3(256), 0, n->stream, n->yout, target, mask, P0, kOutPad, oc,
+                       n->d_red, n->g_out, n->part);
+    hipLaunchKernelGGL(lbm::nn::k_sum_partials, dim3(1), dim3(256), 0, n->stream, n->part, nb, n->d_red + 1);
+    LBM_HIP_TRY(hipGetLastError());
+    LBM_HIP_TRY(hipMemcpyAsync(n->h_red, n->d_red, 2 * sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    // 1x1 output convolution (no activation)
+    const CSlice top = L == 1 ? cs(v0.e2, v0.C) : cs(v0.d2o, v0.C);
+    const Slice g_top = L == 1 ? sl(v0.g_e2, v0.C) : sl(v0.g_d2o, v0.C);
+    LBM_HIP_TRY(wgrad(n, n->out, top, cs(n->g_out, kOutPad), N, v0.H, v0.W));
+    LBM_HIP_TRY(lbm::nn::conv_dgrad(cs(n->g_out, kOutPad), n->out.wt, g_top, N, v0.H, v0.W, n->out.cin, n->out.cout,
+                                    1, false, n->stream));
+    // decoder, level 0 up to the level above the bottleneck
+    for (int l = 0; l <= L - 2; ++l) {
+        Level& v = n->lv[l];
+        Level& below = n->lv[l + 1];
+        const int cup = chan(n, l + 1), ccat = cup + v.C;
+        LBM_HIP_TRY(conv_relu_bwd(n, v.d2, cs(v.d1o, v.C), cs(v.d2o, v.C), cs(v.g_d2o, v.C), sl(v.g_d1o, v.C), N, v.H,
+                                  v.W));
+        LBM_HIP_TRY(conv_relu_bwd(n, v.d1, cs(v.cat, ccat), cs(v.d1o, v.C), cs(v.g_d1o, v.C), sl(v.g_cat, ccat), N,
+                                  v.H, v.W));
+        // upsampled part of the concatenation -> gradient of the level below's output
+        const Slice gsrc = l == L - 2 ? sl(below.g_e2, below.C) : sl(below.g_d2o, below.C);
+        hipLaunchKernelGGL(lbm::nn::k_up_bwd, dim3(lbm::nn::blocks(size_t(N) * below.H * below.W * cup)), dim3(256),
+                           0, n->stream, cs(v.g_cat, ccat, 0), gsrc, N, below.H, below.W, cup);
+        LBM_HIP_TRY(hipGetLastError());
+    }
+    // encoder, bottleneck down to level 0; the skip gradients already sit in the concatenation
+    // gradients, and the pooling gradients are added to them on the way
+    for (int l = L - 1; l >= 0; --l) {
+        Level& v = n->lv[l];
+        const int cup = l < L - 1 ? chan(n, l + 1) : 0;
+        const CSlice y2 = l < L - 1 ? cs(v.cat, cup + v.C, cup) : cs(v.e2, v.C);
+        const CSlice g2 = l < L - 1 ? cs(v.g_cat, cup + v.C, cup) : cs(v.g_e2, v.C);
+        LBM_HIP_TRY(conv_relu_bwd(n, v.c2, cs(v.e1, v.C), y2, g2, sl(v.g_e1, v.C), N, v.H, v.W));
+        const Slice gin = l > 0 ? sl(v.g_in, v.cin) : Slice{nullptr, 0, 0};
+        LBM_HIP_TRY(conv_relu_bwd(n, v.c1, cs(v.in, v.cin), cs(v.e1, v.C), cs(v.g_e1, v.C), gin, N, v.H, v.W));
+        if (l > 0) {
+            Level& up = n->lv[l - 1];
+            const Slice g_skip = sl(up.g_cat, chan(n, l) + up.C, chan(n, l));
+            hipLaunchKernelGGL(lbm::nn::k_pool_bwd_add, dim3(lbm::nn::blocks(size_t(N) * up.H * up.W * up.C)),
+                               dim3(256), 0, n->stream, cs(v.g_in, v.cin), g_skip, N, up.H, up.W, up.C);
+            LBM_HIP_TRY(hipGetLastError());
+        }
+    }
+    LBM_HIP_TRY(hipStreamSynchronize(n->stream));
+    if (loss) *loss = n->h_red[1] / (std::max(n->h_red[0], 1.0) * oc);
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_adam_step(lbm_nn* n, float lr, float beta1, float beta2, float eps)
+{
+    if (!n) return fail(LBM_E_INVAL, "null network");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(LBM_E_INVAL, "Adam hyper-parameters out of range");
+    DeviceGuard g(n->device);
+    n->adam_t += 1;
+    const float c1 = 1.f - std::pow(beta1, float(n->adam_t)), c2 = 1.f - std::pow(beta2, float(n->adam_t));
+    hipLaunchKernelGGL(lbm::nn::k_adam, dim3(lbm::nn::blocks(n->n_params)), dim3(256), 0, n->stream, n->w, n->m, n->v,
+                       n->g, n->wb, n->n_params, lr, beta1, beta2, eps, c1, c2);
+    LBM_HIP_TRY(hipGetLastError());
+    LBM_HIP_TRY(refresh_flipped(n));
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_features(const uint8_t* solid, const lbm_link* links, int64_t n_links, int32_t nx, int32_t ny,
+                           float kn_feature, float ax_feature, float ay_feature, void* out, int32_t channels,
+                           void* stream)
+{
+    if (!solid || !out || (n_links > 0 && !links)) return fail(LBM_E_INVAL, "null argument");
+    if (nx < 1 || ny < 1 || int64_t(nx) * ny > INT32_MAX / 64 || n_links < 0 || channels < 16 || channels % 8 ||
+        channels > 4096)
+        return fail(LBM_E_INVAL, "feature sizes out of range");
+    if (!aligned16(out)) return fail(LBM_E_INVAL, "output needs 16-byte alignment");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = nx * ny;
+    bf16* x = static_cast<bf16*>(out);
+    hipLaunchKernelGGL(lbm::nn::k_feat_sites, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, solid, n, kn_feature,
+                       ax_feature, ay_feature, x, channels);
+    if (n_links > 0)
+        hipLaunchKernelGGL(lbm::nn::k_feat_links, dim3(lbm::nn::blocks(size_t(n_links))), dim3(256), 0, st, links,
+                           n_links, solid, nx, ny, x, channels);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_fields(const float* pred, int32_t stride, const uint8_t* solid, int32_t nx, int32_t ny,
+                         double u_scale, double rho_scale, double rho0, double* rho, double* ux, double* uy,
+                         int64_t* n_bad, void* stream)
+{
+    if (!pred || !solid || !rho || !ux || !uy || !n_bad) return fail(LBM_E_INVAL, "null argument");
+    if (nx < 1 || ny < 1 || int64_t(nx) * ny > INT32_MAX / 8 || stride < 3)
+        return fail(LBM_E_INVAL, "sizes out of range");
+    if (!std::isfinite(u_scale) || !std::isfinite(rho_scale) || !std::isfinite(rho0))
+        return fail(LBM_E_INVAL, "non-finite scale");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    long long* d_bad = nullptr;
+    LBM_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d_bad), sizeof(long long)));
+    hipLaunchKernelGGL(lbm::nn::k_fields, dim3(1), dim3(1024), 0, st, pred, stride, solid, nx * ny, u_scale, rho_scale,
+                       rho0, rho, ux, uy, d_bad);
+    long long h_bad = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, d_bad, sizeof(long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    ignore(hipFree(d_bad));
+    if (e != hipSuccess) return fail(LBM_E_HIP, "lbm_nn_fields: %s", hipGetErrorString(e));
+    *n_bad = h_bad;
+    return LBM_OK;
+}
+
+}  // extern "C"

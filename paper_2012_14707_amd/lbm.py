@@ -60,6 +60,12 @@ class BatchLaunch(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class NnConfig(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("base_channels", C.c_int32), ("in_channels", C.c_int32),
+                ("out_channels", C.c_int32), ("height", C.c_int32), ("width", C.c_int32),
+                ("max_batch", C.c_int32), ("periodic", C.c_int32)]
+
+
 BATCH_STATUS = {0: "running", 1: "converged", 2: "floor", 3: "capped", 4: "diverged"}
 
 # Every entry point of include/lbm.h with its ctypes signature.
@@ -96,6 +102,23 @@ SIGNATURES = {
     "lbm_batch_set_launch": (C.c_int32, [_VP, C.POINTER(BatchLaunch)]),
     "lbm_batch_get_launch": (C.c_int32, [_VP, C.POINTER(BatchLaunch)]),
     "lbm_batch_tune": (C.c_int32, [_VP, C.c_char_p, C.c_int32, C.POINTER(BatchLaunch)]),
+    "lbm_conv2d_forward": (C.c_int32, [_VP, _VP, _VP, _VP, _VP] + [C.c_int32] * 8 + [_VP]),
+    "lbm_conv2d_dgrad": (C.c_int32, [_VP, _VP, _VP, _VP] + [C.c_int32] * 7 + [_VP]),
+    "lbm_conv2d_wgrad_workspace": (C.c_int32, [C.c_int32] * 6 + [C.POINTER(C.c_int64)]),
+    "lbm_conv2d_wgrad": (C.c_int32, [_VP, _VP, _VP, _VP, _VP, C.c_int64] + [C.c_int32] * 7 + [_VP]),
+    "lbm_nn_create": (C.c_int32, [C.POINTER(NnConfig), C.c_uint64, _VP, C.POINTER(_VP)]),
+    "lbm_nn_destroy": (C.c_int32, [_VP]),
+    "lbm_nn_param_count": (C.c_int32, [_VP, C.POINTER(C.c_int64)]),
+    "lbm_nn_set_params": (C.c_int32, [_VP, _VP]),
+    "lbm_nn_get_params": (C.c_int32, [_VP, _VP]),
+    "lbm_nn_get_grads": (C.c_int32, [_VP, _VP]),
+    "lbm_nn_forward": (C.c_int32, [_VP, _VP, _VP, C.c_int32]),
+    "lbm_nn_backward": (C.c_int32, [_VP, _VP, _VP, C.c_int32, _DPTR]),
+    "lbm_nn_adam_step": (C.c_int32, [_VP, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "lbm_nn_features": (C.c_int32, [_VP, _VP, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                    _VP, C.c_int32, _VP]),
+    "lbm_nn_fields": (C.c_int32, [_VP, C.c_int32, _VP, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                  _VP, _VP, _VP, C.POINTER(C.c_int64), _VP]),
 }
 
 _lib = None
@@ -366,3 +389,144 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         _check(self._lib.lbm_batch_tune(self._h, path, int(trial_steps), C.byref(lb)))
         return dict(block=lb.block, graph_steps=lb.graph_steps, blocks_per_cu=lb.blocks_per_cu)
+
+
+# ------------------------------------------------------------------------------ warm-start network
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def conv2d_forward(x, w, bias=None, out=None, out32=None, relu=False, periodic=False, stream=None):
+    """lbm_conv2d_forward on NHWC torch tensors: x bf16 [n,h,w,cin], w bf16 [k*k,cout,cin]."""
+    import torch
+    n, h, wd, cin = x.shape
+    kk, cout, cin2 = w.shape
+    assert cin2 == cin and x.dtype == w.dtype == torch.bfloat16
+    assert out is None or (tuple(out.shape) == (n, h, wd, cout) and out.dtype == torch.bfloat16)
+    assert out32 is None or (tuple(out32.shape) == (n, h, wd, cout) and out32.dtype == torch.float32)
+    assert bias is None or (bias.numel() == cout and bias.dtype == torch.float32)
+    _check(load().lbm_conv2d_forward(_ptr(x), _ptr(w), _ptr(bias), _ptr(out), _ptr(out32), n, h, wd, cin, cout,
+                                     int(round(kk ** 0.5)), int(bool(relu)), int(bool(periodic)), _stream_handle(stream)))
+
+
+def conv2d_dgrad(dout, w, din, periodic=False, stream=None):
+    import torch
+    n, h, wd, cout = dout.shape
+    kk, cout2, cin = w.shape
+    assert cout2 == cout and dout.dtype == w.dtype == din.dtype == torch.bfloat16
+    assert tuple(din.shape) == (n, h, wd, cin)
+    wt = torch.empty_like(w)
+    _check(load().lbm_conv2d_dgrad(_ptr(dout), _ptr(w), _ptr(din), _ptr(wt), n, h, wd, cin, cout,
+                                   int(round(kk ** 0.5)), int(bool(periodic)), _stream_handle(stream)))
+
+
+def conv2d_wgrad(x, dout, dw, db=None, periodic=False, stream=None):
+    import torch
+    n, h, wd, cin = x.shape
+    cout = dout.shape[-1]
+    k = int(round(dw.shape[0] ** 0.5))
+    assert tuple(dout.shape[:3]) == (n, h, wd) and tuple(dw.shape[1:]) == (cout, cin)
+    assert x.dtype == dout.dtype == torch.bfloat16 and dw.dtype == torch.float32
+    assert db is None or (db.numel() == cout and db.dtype == torch.float32)
+    lib = load()
+    need = C.c_int64()
+    _check(lib.lbm_conv2d_wgrad_workspace(n, h, wd, cin, cout, k, C.byref(need)))
+    work = torch.empty(max(int(need.value), 1), dtype=torch.float32, device=x.device)
+    _check(lib.lbm_conv2d_wgrad(_ptr(x), _ptr(dout), _ptr(dw), _ptr(db), _ptr(work), int(need.value), n, h, wd, cin,
+                                cout, k, int(bool(periodic)), _stream_handle(stream)))
+
+
+def nn_features(solid, links, nx, ny, kn_feature, ax_feature, ay_feature, out, stream=None):
+    """lbm_nn_features: solid uint8 [ny, nx] and links (structured uint8 bytes of lbm_link) on the device."""
+    import torch
+    n_links = links.numel() // C.sizeof(Link) if links is not None else 0
+    assert tuple(solid.shape) == (ny, nx) and solid.dtype == torch.uint8
+    assert tuple(out.shape[:2]) == (ny, nx) and out.dtype == torch.bfloat16
+    assert links is None or (links.dtype == torch.uint8 and links.numel() == n_links * C.sizeof(Link))
+    _check(load().lbm_nn_features(_ptr(solid), _ptr(links) if n_links else None, n_links, nx, ny, float(kn_feature),
+                                  float(ax_feature), float(ay_feature), _ptr(out), out.shape[-1],
+                                  _stream_handle(stream)))
+
+
+def nn_fields(pred, solid, nx, ny, u_scale, rho_scale, rho0, rho, ux, uy, stream=None):
+    """lbm_nn_fields; returns the number of fluid sites with a non-finite prediction."""
+    import torch
+    assert pred.dtype == torch.float32 and pred.numel() == nx * ny * pred.shape[-1] and pred.shape[-1] >= 3
+    assert solid.numel() == nx * ny and solid.dtype == torch.uint8
+    assert all(t.numel() == nx * ny and t.dtype == torch.float64 for t in (rho, ux, uy))
+    bad = C.c_int64()
+    _check(load().lbm_nn_fields(_ptr(pred), pred.shape[-1], _ptr(solid), nx, ny, float(u_scale), float(rho_scale),
+                                float(rho0), _ptr(rho), _ptr(ux), _ptr(uy), C.byref(bad), _stream_handle(stream)))
+    return int(bad.value)
+
+
+class Net:
+    """The warm-start encoder-decoder of liblbm (lbm_nn_* of include/lbm.h)."""
+
+    def __init__(self, levels=5, base_channels=32, in_channels=12, out_channels=3, height=256, width=256,
+                 max_batch=8, periodic=False, seed=0, stream=None):
+        lib = load()
+        self._lib = lib
+        self.cfg = NnConfig(levels, base_channels, in_channels, out_channels, height, width, max_batch,
+                            int(bool(periodic)))
+        self.in_pad = (in_channels + 7) // 8 * 8
+        h = C.c_void_p()
+        _check(lib.lbm_nn_create(C.byref(self.cfg), int(seed), _stream_handle(stream), C.byref(h)))
+        self._h = h
+        cnt = C.c_int64()
+        _check(lib.lbm_nn_param_count(h, C.byref(cnt)))
+        self.n_params = int(cnt.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbm_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        a = np.zeros(self.n_params, np.float32)
+        _check(self._lib.lbm_nn_get_params(self._h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(self._lib.lbm_nn_set_params(self._h, a.ctypes.data_as(C.c_void_p)))
+
+    def get_grads(self):
+        a = np.zeros(self.n_params, np.float32)
+        _check(self._lib.lbm_nn_get_grads(self._h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def forward(self, x, out=None):
+        """x: bf16 device tensor [n, h, w, in_pad]; out: fp32 [n, h, w, out_channels] or None."""
+        import torch
+        n = int(x.shape[0])
+        assert tuple(x.shape) == (n, self.cfg.height, self.cfg.width, self.in_pad) and x.dtype == torch.bfloat16
+        assert out is None or (tuple(out.shape) == (n, self.cfg.height, self.cfg.width, self.cfg.out_channels)
+                               and out.dtype == torch.float32)
+        _check(self._lib.lbm_nn_forward(self._h, _ptr(x), _ptr(out), int(x.shape[0])))
+        return out
+
+    def backward(self, target, mask):
+        import torch
+        n = int(mask.shape[0])
+        assert tuple(mask.shape) == (n, self.cfg.height, self.cfg.width) and mask.dtype == torch.uint8
+        assert tuple(target.shape) == (n, self.cfg.height, self.cfg.width, self.cfg.out_channels)
+        assert target.dtype == torch.float32
+        loss = C.c_double()
+        _check(self._lib.lbm_nn_backward(self._h, _ptr(target), _ptr(mask), int(mask.shape[0]), C.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(self._lib.lbm_nn_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))

@@ -38,7 +38,7 @@ def test_struct_layouts(tmp_path):
     src = tmp_path / "layout.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
     for cname, py in (("lbm_link", lbm.Link), ("lbm_params", lbm.Params), ("lbm_info", lbm.Info),
-                      ("lbm_batch_launch", lbm.BatchLaunch)):
+                      ("lbm_batch_launch", lbm.BatchLaunch), ("lbm_nn_config", lbm.NnConfig)):
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
@@ -49,7 +49,7 @@ def test_struct_layouts(tmp_path):
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                        check=True).stdout.splitlines())
     for cname, py in (("lbm_link", lbm.Link), ("lbm_params", lbm.Params), ("lbm_info", lbm.Info),
-                      ("lbm_batch_launch", lbm.BatchLaunch)):
+                      ("lbm_batch_launch", lbm.BatchLaunch), ("lbm_nn_config", lbm.NnConfig)):
         assert int(out[cname]) == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
