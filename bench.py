@@ -181,6 +181,37 @@ def batched_sweep(steps=2000, solve_cap=100_000, tol=1e-8):
     }
 
 
+def warm_start(n_eval=40, tol=1e-8):
+    """Learned warm start against rest on held-out 256^2 random-cylinder problems (FP64 solves to
+    residual <= tol; wall time includes features, inference, fields and initialisation), and the
+    throughput of the network's forward pass on the matrix cores."""
+    import torch
+    from paper_2012_14707_amd import warmstart as W
+    model = W.Model.load(W.DEFAULT_MODEL, max_batch=8)
+    pbs = W.instances(W.TEST_SEEDS[:n_eval], workers=1)
+    rows = [W.compare(pb, model, tol) for pb in pbs]
+    out = W.summarize(rows)
+    # forward pass of a batch of 8 images, timed with HIP events on the network's stream
+    x = torch.zeros((8, W.SIDE, W.SIDE, W.IN_PAD), dtype=torch.bfloat16, device="cuda")
+    for i in range(8):
+        W.features_into(pbs[i % len(pbs)], x[i])
+    for _ in range(3):
+        model.net.forward(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        model.net.forward(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = W.forward_flops(batch=8)
+    out.update(precision="fp64", tol=tol, seeds=f"{W.TEST_SEEDS[0]}..{W.TEST_SEEDS[0] + n_eval - 1}",
+               nn_forward_ms_batch8=round(ms, 3), nn_forward_tflops=round(flops / (ms * 1e-3) / 1e12, 1),
+               nn_forward_frac_bf16_peak=round(flops / (ms * 1e-3) / 1e12 / 2500.0, 4))
+    return {k: (round(v, 4) if isinstance(v, float) and k != "tol" else v) for k, v in out.items()}
+
+
 def cpu_baseline(problem, steps=2):
     """The oracle as it stands on this host's cores: `steps` steps of the full lattice."""
     import oracle
@@ -207,6 +238,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sweep measurement")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (20 times) to scale HBM counters")
     args = ap.parse_args()
@@ -293,6 +325,12 @@ def main():
     if not args.no_batched and not args.only:
         log("[bench] batched sweep (256 uneven instances)")
         line["batched"] = batched_sweep()
+    if not args.no_warm_start and not args.only:
+        log("[bench] learned warm start vs rest (40 held-out 256^2 problems, FP64 to residual 1e-8)")
+        line["warm_start"] = warm_start()
+        w = line["warm_start"]
+        log(f"[bench] warm start: step ratio median {w['step_ratio_median']}, wall ratio median "
+            f"{w['wall_ratio_median']}, forward {w['nn_forward_tflops']} TFLOP/s")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle, 2 steps of the full lattice on the host cores")
         line["cpu_baseline"] = cpu_baseline(pb)

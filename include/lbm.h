@@ -362,14 +362,17 @@ lbm_status lbm_nn_features(const uint8_t *solid, const lbm_link *links, int64_t 
                            void *stream);
 
 /* Initial fields from one image of network output pred fp32 [ny * nx, stride] (channels: u_x, u_y,
- * delta rho, normalised): on fluid sites ux = u_scale pred0, uy = u_scale pred1,
- * rho = rho0 + rho_scale (pred2 - mean of pred2 over fluid sites), so that the total mass equals
- * that of the rest state; solid sites get rho0 and 0.  rho, ux, uy: fp64 [ny * nx].  *n_bad (host)
- * = number of fluid sites with a non-finite prediction (the caller falls back to rest if > 0).
- * Synchronises the stream. */
+ * delta rho, normalised).  The three channels are taken on fluid sites (0 on solid sites) and
+ * smoothed smooth_iters times, each pass replacing the value at a fluid site by the mean over the
+ * fluid sites of its 3 x 3 neighbourhood (wrapping around the edges if periodic, else bounded by
+ * them); then on fluid sites ux = u_scale t0, uy = u_scale t1, rho = rho0 + rho_scale (t2 - mean
+ * of t2 over fluid sites), so that the total mass equals that of the rest state; solid sites get
+ * rho0 and 0.  rho, ux, uy: fp64 [ny * nx].  *n_bad (host) = number of fluid sites with a
+ * non-finite value after smoothing (the caller falls back to rest if > 0).  Allocates and frees
+ * 48 bytes of device memory per site; synchronises the stream. */
 lbm_status lbm_nn_fields(const float *pred, int32_t stride, const uint8_t *solid, int32_t nx, int32_t ny,
-                         double u_scale, double rho_scale, double rho0, double *rho, double *ux, double *uy,
-                         int64_t *n_bad, void *stream);
+                         int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale, double rho0,
+                         double *rho, double *ux, double *uy, int64_t *n_bad, void *stream);
 
 #ifdef __cplusplus
 }

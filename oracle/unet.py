@@ -170,14 +170,46 @@ def features(solid, links, kn_feature, ax_feature, ay_feature, channels=16):
     return f
 
 
-def fields(pred, solid, u_scale, rho_scale, rho0):
-    """Initial (rho, ux, uy) from one predicted image (ny, nx, 3): on fluid sites u = u_scale
-    pred[..., :2] and rho = rho0 + rho_scale (pred[..., 2] - its fluid mean); rho0 and 0 on solid."""
+def smooth(planes, solid, periodic):
+    """One pass of the masked 3 x 3 mean: at each fluid site, the mean of every plane over the fluid
+    sites of its neighbourhood (indices modulo the image size if periodic, else inside the image);
+    0 on solid sites.  planes: list of (ny, nx) arrays."""
+    solid = np.asarray(solid) != 0
+    ny, nx = solid.shape
+    out = [np.zeros((ny, nx)) for _ in planes]
+    for y in range(ny):
+        for x in range(nx):
+            if solid[y, x]:
+                continue
+            acc = [0.0] * len(planes)
+            cnt = 0
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    yy, xx = y + dy, x + dx
+                    if periodic:
+                        yy, xx = yy % ny, xx % nx
+                    if not (0 <= yy < ny and 0 <= xx < nx) or solid[yy, xx]:
+                        continue
+                    cnt += 1
+                    for c, p in enumerate(planes):
+                        acc[c] += p[yy, xx]
+            for c in range(len(planes)):
+                out[c][y, x] = acc[c] / cnt
+    return out
+
+
+def fields(pred, solid, u_scale, rho_scale, rho0, smooth_iters=0, periodic=False):
+    """Initial (rho, ux, uy) from one predicted image (ny, nx, 3): the three channels on fluid
+    sites, smoothed smooth_iters times (see smooth), then u = u_scale (t0, t1) and
+    rho = rho0 + rho_scale (t2 - its fluid mean) on fluid sites; rho0 and 0 on solid sites."""
     solid = np.asarray(solid) != 0
     pred = np.asarray(pred, dtype=np.float64)
     fl = ~solid
-    mean = pred[..., 2][fl].mean() if fl.any() else 0.0
-    rho = np.where(fl, rho0 + rho_scale * (pred[..., 2] - mean), rho0)
-    ux = np.where(fl, u_scale * pred[..., 0], 0.0)
-    uy = np.where(fl, u_scale * pred[..., 1], 0.0)
+    t = [np.where(fl, pred[..., c], 0.0) for c in range(3)]
+    for _ in range(smooth_iters):
+        t = smooth(t, solid, periodic)
+    mean = t[2][fl].mean() if fl.any() else 0.0
+    rho = np.where(fl, rho0 + rho_scale * (t[2] - mean), rho0)
+    ux = np.where(fl, u_scale * t[0], 0.0)
+    uy = np.where(fl, u_scale * t[1], 0.0)
     return rho, ux, uy

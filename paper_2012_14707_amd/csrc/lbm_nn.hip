@@ -447,20 +447,59 @@ __global__ void __launch_bounds__(256) k_feat_links(const lbm_link* links, int64
     x[s * C + l.dir] = bf16(float(l.q));
 }
 
-// One block: mean of the predicted density deviation over fluid sites (fp64, fixed order), then
-// the fields.  bad[0] = fluid sites with a non-finite prediction.
-__global__ void __launch_bounds__(1024) k_fields(const float* pred, int stride, const uint8_t* solid, int n, double us,
-                                                 double rs, double rho0, double* rho, double* ux, double* uy,
-                                                 long long* bad)
+// Unpacks one predicted image into three fp64 planes (u_x, u_y, density deviation) over fluid
+// sites, 0 on solid sites.
+__global__ void __launch_bounds__(256) k_unpack(const float* pred, int stride, const uint8_t* solid, int n, double* t)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const bool fl = !solid[s];
+    for (int c = 0; c < 3; ++c) t[size_t(c) * n + s] = fl ? double(pred[size_t(s) * stride + c]) : 0.0;
+}
+
+// One smoothing pass: at a fluid site, the mean of the three planes over the fluid sites of its
+// 3 x 3 neighbourhood (rows and columns wrap around when periodic, else the image edge bounds
+// the neighbourhood); 0 on solid sites.
+__global__ void __launch_bounds__(256) k_smooth(const double* in, double* out, const uint8_t* solid, int nx, int ny,
+                                                int periodic)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int n = nx * ny;
+    if (s >= n) return;
+    const int y = s / nx, x = s - y * nx;
+    double acc[3] = {0.0, 0.0, 0.0};
+    int cnt = 0;
+    if (!solid[s]) {
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int yy = y + dy, xx = x + dx;
+                if (periodic) {
+                    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+                    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+                }
+                if (yy < 0 || yy >= ny || xx < 0 || xx >= nx) continue;
+                const int q = yy * nx + xx;
+                if (solid[q]) continue;
+                ++cnt;
+                for (int c = 0; c < 3; ++c) acc[c] += in[size_t(c) * n + q];
+            }
+    }
+    for (int c = 0; c < 3; ++c) out[size_t(c) * n + s] = cnt ? acc[c] / cnt : 0.0;
+}
+
+// One block: mean of the density deviation over fluid sites (fp64, fixed order), then the
+// fields.  bad[0] = fluid sites with a non-finite value.
+__global__ void __launch_bounds__(1024) k_fields(const double* t, const uint8_t* solid, int n, double us, double rs,
+                                                 double rho0, double* rho, double* ux, double* uy, long long* bad)
 {
     __shared__ double s_sum[1024];
     __shared__ int s_cnt[1024], s_bad[1024];
-    const int t = threadIdx.x;
+    const int tid = threadIdx.x;
     double sum = 0.0;
     int cnt = 0, nb = 0;
-    for (int s = t; s < n; s += 1024) {
+    for (int s = tid; s < n; s += 1024) {
         if (solid[s]) continue;
-        const float a = pred[size_t(s) * stride], b = pred[size_t(s) * stride + 1], c = pred[size_t(s) * stride + 2];
+        const double a = t[s], b = t[size_t(n) + s], c = t[2 * size_t(n) + s];
         if (!isfinite(a) || !isfinite(b) || !isfinite(c)) {
             ++nb;
         } else {
@@ -468,31 +507,31 @@ __global__ void __launch_bounds__(1024) k_fields(const float* pred, int stride, 
             ++cnt;
         }
     }
-    s_sum[t] = sum;
-    s_cnt[t] = cnt;
-    s_bad[t] = nb;
+    s_sum[tid] = sum;
+    s_cnt[tid] = cnt;
+    s_bad[tid] = nb;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) {
-            s_sum[t] += s_sum[t + w];
-            s_cnt[t] += s_cnt[t + w];
-            s_bad[t] += s_bad[t + w];
+        if (tid < w) {
+            s_sum[tid] += s_sum[tid + w];
+            s_cnt[tid] += s_cnt[tid + w];
+            s_bad[tid] += s_bad[tid + w];
         }
         __syncthreads();
     }
     const double mean = s_cnt[0] ? s_sum[0] / s_cnt[0] : 0.0;
-    for (int s = t; s < n; s += 1024) {
+    for (int s = tid; s < n; s += 1024) {
         if (solid[s]) {
             rho[s] = rho0;
             ux[s] = 0.0;
             uy[s] = 0.0;
         } else {
-            rho[s] = rho0 + rs * (double(pred[size_t(s) * stride + 2]) - mean);
-            ux[s] = us * double(pred[size_t(s) * stride]);
-            uy[s] = us * double(pred[size_t(s) * stride + 1]);
+            rho[s] = rho0 + rs * (t[2 * size_t(n) + s] - mean);
+            ux[s] = us * t[s];
+            uy[s] = us * t[size_t(n) + s];
         }
     }
-    if (t == 0) bad[0] = s_bad[0];
+    if (tid == 0) bad[0] = s_bad[0];
 }
 
 inline unsigned blocks(size_t n) { return unsigned((n + 255) / 256); }
@@ -1048,24 +1087,36 @@ lbm_status lbm_nn_features(const uint8_t* solid, const lbm_link* links, int64_t 
 }
 
 lbm_status lbm_nn_fields(const float* pred, int32_t stride, const uint8_t* solid, int32_t nx, int32_t ny,
-                         double u_scale, double rho_scale, double rho0, double* rho, double* ux, double* uy,
-                         int64_t* n_bad, void* stream)
+                         int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale, double rho0,
+                         double* rho, double* ux, double* uy, int64_t* n_bad, void* stream)
 {
     if (!pred || !solid || !rho || !ux || !uy || !n_bad) return fail(LBM_E_INVAL, "null argument");
-    if (nx < 1 || ny < 1 || int64_t(nx) * ny > INT32_MAX / 8 || stride < 3)
-        return fail(LBM_E_INVAL, "sizes out of range");
+    if (nx < 1 || ny < 1 || int64_t(nx) * ny > INT32_MAX / 8 || stride < 3 || smooth_iters < 0 ||
+        smooth_iters > 1000 || (periodic != 0 && periodic != 1))
+        return fail(LBM_E_INVAL, "arguments out of range");
     if (!std::isfinite(u_scale) || !std::isfinite(rho_scale) || !std::isfinite(rho0))
         return fail(LBM_E_INVAL, "non-finite scale");
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    long long* d_bad = nullptr;
-    LBM_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d_bad), sizeof(long long)));
-    hipLaunchKernelGGL(lbm::nn::k_fields, dim3(1), dim3(1024), 0, st, pred, stride, solid, nx * ny, u_scale, rho_scale,
-                       rho0, rho, ux, uy, d_bad);
+    const int n = nx * ny;
+    void* work = nullptr;  // two sets of three fp64 planes, then the count
+    LBM_HIP_TRY(hipMalloc(&work, sizeof(double) * 6 * size_t(n) + sizeof(long long)));
+    double* t0 = static_cast<double*>(work);
+    double* t1 = t0 + 3 * size_t(n);
+    long long* d_bad = reinterpret_cast<long long*>(t1 + 3 * size_t(n));
+    hipLaunchKernelGGL(lbm::nn::k_unpack, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, pred, stride, solid, n,
+                       t0);
+    for (int i = 0; i < smooth_iters; ++i) {
+        hipLaunchKernelGGL(lbm::nn::k_smooth, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, t0, t1, solid, nx, ny,
+                           periodic);
+        std::swap(t0, t1);
+    }
+    hipLaunchKernelGGL(lbm::nn::k_fields, dim3(1), dim3(1024), 0, st, t0, solid, n, u_scale, rho_scale, rho0, rho, ux,
+                       uy, d_bad);
     long long h_bad = 0;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, d_bad, sizeof(long long), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    ignore(hipFree(d_bad));
+    ignore(hipFree(work));
     if (e != hipSuccess) return fail(LBM_E_HIP, "lbm_nn_fields: %s", hipGetErrorString(e));
     *n_bad = h_bad;
     return LBM_OK;

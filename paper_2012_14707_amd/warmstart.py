@@ -42,6 +42,10 @@ NET_SHAPE = dict(levels=5, base_channels=32, in_channels=IN_CHANNELS, out_channe
                  width=SIDE, periodic=True)
 TRAIN_SEEDS = range(1000, 3000)
 TEST_SEEDS = range(9000, 9200)
+# Passes of the masked 3 x 3 mean applied to the prediction before it initialises the lattice: the
+# network's pixel-scale error (and the bf16 rounding of its activations) would otherwise excite
+# grid-scale oscillations of the populations that keep the step-to-step residual up.
+SMOOTH_ITERS = 4
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_MODEL = os.path.join(HERE, "weights", "warmstart_256.npz")
 
@@ -165,7 +169,8 @@ class Model:
         self.net.forward(x, y)
         us, rs = reference_scales(pb, nu)
         rho, ux, uy = (torch.empty((SIDE, SIDE), dtype=torch.float64, device="cuda") for _ in range(3))
-        bad = lbm.nn_fields(y, solid, SIDE, SIDE, us * self.u_gain, rs * self.rho_gain, rho0, rho, ux, uy)
+        bad = lbm.nn_fields(y, solid, SIDE, SIDE, us * self.u_gain, rs * self.rho_gain, rho0, rho, ux, uy,
+                            smooth_iters=SMOOTH_ITERS, periodic=True)
         return rho, ux, uy, bad
 
 
@@ -187,6 +192,21 @@ def _bias_mask(n_params):
         off += co
     assert off == n_params
     return m
+
+
+def forward_flops(shape=None, batch=1):
+    """Multiply-add count x 2 of one forward pass (padded channels included, as computed)."""
+    shape = shape or NET_SHAPE
+    c, L = shape["base_channels"], shape["levels"]
+    cin0 = (shape["in_channels"] + 7) // 8 * 8
+    total = 0
+    for l in range(L):
+        px = (shape["height"] >> l) * (shape["width"] >> l)
+        total += 2 * px * 9 * ((cin0 if l == 0 else c << (l - 1)) + (c << l)) * (c << l)
+        if l < L - 1:
+            total += 2 * px * 9 * ((c << (l + 1)) + 2 * (c << l)) * (c << l)
+    total += 2 * shape["height"] * shape["width"] * c * 8
+    return total * batch
 
 
 # ------------------------------------------------------------------------------------ data
@@ -245,13 +265,19 @@ def _masked_mse(y, t, m):
     return float(d.pow(2).mean())
 
 
-# Mirror y -> ny-1-y of the features: link directions N<->S, NE<->SE, NW<->SW swap, a_y changes sign.
+# Mirrors of the feature channels: y -> -y swaps the link directions N<->S, NE<->SE, NW<->SW;
+# x -> -x swaps E<->W, NE<->NW, SE<->SW.
 _YFLIP_CHANNELS = [0, 1, 4, 3, 2, 8, 7, 6, 5, 9, 10, 11, 12, 13, 14, 15]
+_XFLIP_CHANNELS = [0, 3, 2, 1, 4, 6, 5, 8, 7, 9, 10, 11, 12, 13, 14, 15]
 
 
-def augment(x, t, m, rng):
+def augment(x, t, m, rng, xflip=True):
     """A random symmetry of the doubly periodic problem class applied to a batch: a periodic
-    shift and, with probability 1/2, the mirror y -> -y (u_y and a_y change sign)."""
+    shift; with probability 1/2 the mirror y -> -y (u_y and a_y change sign); and, if xflip,
+    with probability 1/2 the mirror x -> -x combined with reversing the force, which by the
+    linearity of creeping flow leaves a_x and u_x as they are and changes the sign of u_y and
+    of the density deviation (exact for Stokes flow, approximate at the small Reynolds numbers
+    of the workload)."""
     import torch
     dy, dx = (int(v) for v in rng.integers(0, SIDE, 2))
     x, t, m = (torch.roll(a, shifts=(dy, dx), dims=(1, 2)) for a in (x, t, m))
@@ -261,10 +287,17 @@ def augment(x, t, m, rng):
         x[..., 11] = -x[..., 11]
         t = torch.flip(t, dims=(1,)) * torch.tensor([1.0, -1.0, 1.0], device=t.device)
         m = torch.flip(m, dims=(1,))
+    if xflip and rng.random() < 0.5:
+        idx = torch.tensor(_XFLIP_CHANNELS, device=x.device)
+        x = torch.flip(x, dims=(2,)).index_select(3, idx)
+        x[..., 11] = -x[..., 11]
+        t = torch.flip(t, dims=(2,)) * torch.tensor([1.0, -1.0, -1.0], device=t.device)
+        m = torch.flip(m, dims=(2,))
     return x.contiguous(), t.contiguous(), m.contiguous()
 
 
-def train(data, test=None, epochs=30, batch=8, lr=1e-3, lr_final=2e-5, seed=0, augment_data=True, log=print):
+def train(data, test=None, epochs=30, batch=8, lr=1e-3, lr_final=2e-5, seed=0, augment_data=True, xflip=True,
+          log=print):
     """Adam on the masked squared error of the gain-normalised targets; cosine learning-rate decay."""
     import torch
     model = Model.create(max_batch=batch, seed=seed)
@@ -285,7 +318,7 @@ def train(data, test=None, epochs=30, batch=8, lr=1e-3, lr_final=2e-5, seed=0, a
             tb = (data["t"].index_select(0, idx) / gain).contiguous()
             mb = data["m"].index_select(0, idx)
             if augment_data:
-                xb, tb, mb = augment(xb, tb, mb, rng)
+                xb, tb, mb = augment(xb, tb, mb, rng, xflip)
             model.net.forward(xb)
             losses.append(model.net.backward(tb, mb))
             cur = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * it / max(iters, 1)))
@@ -346,6 +379,8 @@ def solve(pb, model=None, tol=1e-8, check_every=100, max_steps=1_000_000, precis
             lat.init_fields(rho, ux, uy)
     else:
         lat.init_rest()
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
     steps = 0
     first = None
     res = math.inf
@@ -367,7 +402,7 @@ def solve(pb, model=None, tol=1e-8, check_every=100, max_steps=1_000_000, precis
             break
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return dict(steps=steps, wall=wall, residual=res, fallback=fallback, converged=res <= tol), lat
+    return dict(steps=steps, wall=wall, init=t_init, residual=res, fallback=fallback, converged=res <= tol), lat
 
 
 def compare(pb, model, tol=1e-8, check_every=100, max_steps=1_000_000, precision="fp64"):
@@ -381,7 +416,8 @@ def compare(pb, model, tol=1e-8, check_every=100, max_steps=1_000_000, precision
     diff = max(np.abs(ux_w - ux_r).max(), np.abs(uy_w - uy_r).max()) / umax
     return dict(seed=pb["meta"].get("seed"), kn=pb["params"]["kn"], porosity=pb["meta"].get("porosity"),
                 rest_steps=rest["steps"], rest_wall=rest["wall"], warm_steps=warm["steps"], warm_wall=warm["wall"],
-                fallback=warm["fallback"], converged=rest["converged"] and warm["converged"], u_rel_diff=diff)
+                warm_init=warm["init"], fallback=warm["fallback"], converged=rest["converged"] and warm["converged"],
+                u_rel_diff=diff)
 
 
 def summarize(rows):
@@ -392,6 +428,7 @@ def summarize(rows):
     ratio = ws / rs
     wr = ww / rw
     return dict(n=len(rows), rest_steps_median=float(np.median(rs)), warm_steps_median=float(np.median(ws)),
+                warm_init_ms_median=float(np.median([r.get("warm_init", 0.0) for r in rows]) * 1e3),
                 step_ratio_median=float(np.median(ratio)), step_ratio_mean=float(ratio.mean()),
                 step_ratio_worst=float(ratio.max()), wall_ratio_median=float(np.median(wr)),
                 wall_ratio_mean=float(wr.mean()), wall_ratio_worst=float(wr.max()),

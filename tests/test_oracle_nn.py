@@ -244,3 +244,43 @@ def test_conv_grads_match_finite_differences(periodic):
         e = e.reshape(w.shape)
         assert (f(x, w + e) - f(x, w - e)) / (2 * h) == pytest.approx(gw.reshape(-1)[i], abs=1e-7)
     assert np.allclose(gb, d.sum(axis=(0, 1, 2)))
+
+
+def test_smoothing_definition():
+    # a constant field on the fluid stays constant; solid sites are 0
+    solid = np.zeros((5, 6), np.uint8)
+    solid[2, 1:4] = 1
+    c = [np.full((5, 6), 2.5), np.full((5, 6), -1.0)]
+    out = U.smooth(c, solid, True)
+    assert np.all(out[0][solid == 0] == 2.5) and np.all(out[1][solid == 0] == -1.0) and np.all(out[0][solid == 1] == 0)
+    # hand-worked corner of a bounded 3 x 3 image with one solid site: the corner (0, 0) averages
+    # its fluid neighbours (0,0), (0,1), (1,0) ((1,1) is solid)
+    solid = np.zeros((3, 3), np.uint8)
+    solid[1, 1] = 1
+    v = np.arange(9.0).reshape(3, 3)
+    got = U.smooth([v], solid, False)[0]
+    assert got[0, 0] == pytest.approx((0 + 1 + 3) / 3)
+    assert got[0, 1] == pytest.approx((0 + 1 + 2 + 3 + 5) / 5)
+    # periodic: the same corner also sees the wrapped row 2 and column 2
+    got = U.smooth([v], solid, True)[0]
+    assert got[0, 0] == pytest.approx((0 + 1 + 2 + 3 + 5 + 6 + 7 + 8) / 8)
+    # against a vectorised masked box filter on a random periodic case
+    rng = np.random.default_rng(0)
+    solid = (rng.random((7, 9)) < 0.3).astype(np.uint8)
+    u = rng.normal(size=(7, 9)) * (solid == 0)
+    w = (solid == 0).astype(float)
+    sm = sum(np.roll(np.roll(u, a, 0), b, 1) for a in (-1, 0, 1) for b in (-1, 0, 1))
+    cn = sum(np.roll(np.roll(w, a, 0), b, 1) for a in (-1, 0, 1) for b in (-1, 0, 1))
+    want = np.where(solid == 0, sm / np.maximum(cn, 1), 0)
+    assert np.allclose(U.smooth([u], solid, True)[0], want, rtol=1e-14, atol=1e-15)
+
+
+def test_fields_smoothing_keeps_rest_mass():
+    rng = np.random.default_rng(3)
+    solid = (rng.random((8, 10)) < 0.3).astype(np.uint8)
+    pred = rng.normal(size=(8, 10, 3))
+    rho, ux, uy = U.fields(pred, solid, 1e-3, 2e-4, 1.0, smooth_iters=3, periodic=True)
+    fl = solid == 0
+    assert rho[fl].sum() == pytest.approx(fl.sum(), rel=1e-15)
+    # three passes shrink the spread of a noise field
+    assert ux[fl].std() < 0.6 * 1e-3 * pred[..., 0][fl].std()
