@@ -99,7 +99,7 @@ typedef struct {
     int32_t n_clamped;    /* links where the l mode reset l */
     int32_t n_nonconvex;  /* links with l outside [max(0, 2 gamma - 1), 2 gamma] (Sec. III.A) */
     int32_t precision;
-    int32_t reserved;
+    int32_t steps_per_launch; /* time steps per launch of the step kernel (see lbm_set_fusion) */
     int64_t bytes_per_step; /* algorithmic HBM bytes of one step: 18 s per fluid node + 5 s per link
                                + 1 flag byte per site + 4 bytes per 64-site chunk (s = 8 or 4) */
     int64_t steps;          /* steps taken since the last initialisation */
@@ -178,6 +178,16 @@ lbm_status lbm_synchronize(lbm_ctx *ctx);
 /* Threads per block of the step kernel: 64, 128, 256 (default), 512 or 1024.  Results do not
  * depend on it.  LBM_E_INVAL if the block's wall links would not fit the LDS staging area. */
 lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block);
+
+/* Time steps per kernel launch.  1: one launch of the fused collide-stream-boundary kernel per
+ * step.  2: one launch advances two steps on 64 x rows tiles, keeping the intermediate time level
+ * in LDS (temporal blocking); this halves the HBM traffic per step, and lbm_step then runs pairs
+ * of steps and a single step for an odd remainder.  Results are bit-identical either way.  The
+ * default is 2 for fp64 storage where the lattice tiles, else 1 (with fp32 storage the two-step
+ * kernel is limited by instruction issue, not by memory, and is not faster).  rows: tile rows (4
+ * or 8; 0 = the largest that fits).  LBM_E_INVAL if 2 is asked and nx is not a multiple of 64, ny
+ * not a multiple of rows, or a tile's wall links do not fit the LDS staging area. */
+lbm_status lbm_set_fusion(lbm_ctx *ctx, int32_t steps_per_launch, int32_t rows);
 
 /* Average duration in milliseconds of the step kernel launches of the last lbm_step call,
  * measured with HIP events on the context's stream (0 if timing is off).  Timing is switched on

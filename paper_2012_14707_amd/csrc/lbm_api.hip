@@ -6,6 +6,8 @@
 // the per-link fp64 precompute on the device.  lbm_step then launches only the fused step kernel.
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -47,6 +49,9 @@ struct lbm_ctx {
     int64_t steps = 0;
     bool uprev_valid = false;
     int block = 256;
+    int fuse = 1;             // time steps per launch of the step kernel: 1, or 2 (two-step kernel)
+    int fuse_rows = 0;        // tile rows of the two-step kernel; 0 = not supported by this lattice
+    uint32_t fuse_links = 0;  // LDS link slots of the two-step kernel (most wall links in one tile)
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_timing = false;
@@ -58,6 +63,31 @@ struct lbm_ctx {
     size_t pop_bytes() const { return (fp32() ? 4 : 8) * size_t(9) * ps; }
     size_t link_bytes() const { return (fp32() ? 4 : 8) * size_t(n_links() > 0 ? n_links() : 1); }
     lbm::Geo geo() const { return lbm::Geo{d_flags, d_chunk, pr.n, pr.nx, pr.ny, pr.nchunks, ps}; }
+    // Most wall links in one 64 x rows tile of the two-step kernel (each tile row is one chunk).
+    uint32_t max_links_per_tile(int rows) const
+    {
+        uint32_t best = 0;
+        const uint32_t tiles_x = pr.nx / lbm::kFuseTX;
+        for (uint32_t ty = 0; ty < pr.ny / uint32_t(rows); ++ty)
+            for (uint32_t tx = 0; tx < tiles_x; ++tx) {
+                uint32_t sum = 0;
+                for (int r = 0; r < rows; ++r) {
+                    const uint32_t ch = ((ty * rows + r) * pr.nx + tx * lbm::kFuseTX) / lbm::kChunk;
+                    sum += uint32_t(pr.chunk[ch + 1] - pr.chunk[ch]);
+                }
+                best = std::max(best, sum);
+            }
+        return best;
+    }
+    // Whether the two-step kernel can run with `rows` tile rows, and its LDS link slots.
+    bool fusion_fits(int rows, uint32_t* links) const
+    {
+        if (pr.nx % lbm::kFuseTX != 0 || rows < 1 || pr.ny % uint32_t(rows) != 0) return false;
+        const uint32_t l = std::max<uint32_t>(max_links_per_tile(rows), 1u);
+        if (lbm::step2_lds_bytes(fp32(), rows, l) > lbm::kMaxLds) return false;
+        *links = l;
+        return true;
+    }
     // Most wall links owned by one block of `blk` sites.
     uint32_t max_links_per_block(int blk) const
     {
@@ -143,6 +173,32 @@ lbm_status step_once(lbm_ctx* c, bool write_u)
     return LBM_OK;
 }
 
+// Two time steps in one launch of the two-step kernel (same results as two step_once calls).
+lbm_status step_pair(lbm_ctx* c, bool write_u)
+{
+    const int src = c->cur, dst = 1 - c->cur;
+    const bool node = c->pr.p.diffuse == LBM_DIFFUSE_NODE;
+    const size_t nl = size_t(std::max<int64_t>(c->n_links(), 1));
+    hipError_t e;
+    if (c->fp32()) {
+        const float* k32 = c->d_coef32;
+        const float* rows[5] = {k32, k32 + nl, k32 + 2 * nl, k32 + 3 * nl, k32 + 4 * nl};
+        lbm::StepArgs<float> a = step_args<float>(c, src, dst, rows);
+        a.lds_links = c->fuse_links;
+        e = lbm::launch_step2_f32(a, c->fuse_rows, write_u, node, c->stream);
+    } else {
+        const double* k64 = c->d_coef64;
+        const double* rows[5] = {k64 + 3 * nl, k64 + 4 * nl, k64 + 5 * nl, k64 + 6 * nl, k64 + 7 * nl};
+        lbm::StepArgs<double> a = step_args<double>(c, src, dst, rows);
+        a.lds_links = c->fuse_links;
+        e = lbm::launch_step2_f64(a, c->fuse_rows, write_u, node, c->stream);
+    }
+    if (e != hipSuccess) return fail(LBM_E_HIP, "two-step launch: %s", hipGetErrorString(e));
+    c->cur = dst;
+    c->steps += 2;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -194,6 +250,19 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
     if (lbm::step_lds_bytes(c->fp32(), c->lds_links) > lbm::kMaxLds) {
         release(c);
         return fail(LBM_E_GEOMETRY, "%u wall links in one 64-site chunk exceed the LDS staging area", c->lds_links);
+    }
+    // two time steps per launch where the lattice tiles into 64 x rows blocks
+    // Two time steps per launch by default where it is faster: fp64 storage, whose single step is
+    // bound by HBM traffic.  The fp32 single step already keeps the vector ALUs about 65% busy and
+    // the two-step kernel issues as many instructions per site update, so it does not gain there.
+    for (int rows : {8, 4}) {
+        uint32_t links = 0;
+        if (c->fusion_fits(rows, &links)) {
+            c->fuse = c->fp32() ? 1 : 2;
+            c->fuse_rows = rows;
+            c->fuse_links = links;
+            break;
+        }
     }
 
     // --- device allocations and uploads ---
@@ -264,6 +333,7 @@ lbm_status lbm_get_info(const lbm_ctx* c, lbm_info* info)
     const int64_t sz = c->fp32() ? 4 : 8;
     info->bytes_per_step = 18 * sz * c->pr.n_fluid + 5 * sz * c->n_links() + int64_t(c->n()) + 4 * int64_t(c->pr.nchunks);
     info->steps = c->steps;
+    info->steps_per_launch = c->fuse;
     return LBM_OK;
 }
 
@@ -329,9 +399,17 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
     if (nsteps == 0) return LBM_OK;
     DeviceGuard g(c->device);
     if (c->timing) LBM_HIP_TRY(hipEventRecord(c->ev0, c->stream));
-    for (int64_t it = 0; it < nsteps; ++it) {
+    for (int64_t it = 0; it < nsteps;) {
         // the last step records u(t) so that lbm_residual can compare it with u(t + 1)
-        lbm_status st = step_once(c, it == nsteps - 1);
+        const int64_t left = nsteps - it;
+        lbm_status st;
+        if (c->fuse == 2 && left >= 2) {
+            st = step_pair(c, left == 2);
+            it += 2;
+        } else {
+            st = step_once(c, left == 1);
+            it += 1;
+        }
         if (st != LBM_OK) return st;
     }
     if (c->timing) {
@@ -418,6 +496,29 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block)
     c->block = block;
     c->lds_links = links;
     return LBM_OK;
+}
+
+lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows)
+{
+    if (!c) return fail(LBM_E_INVAL, "null context");
+    if (steps_per_launch == 1) {
+        c->fuse = 1;
+        return LBM_OK;
+    }
+    if (steps_per_launch != 2) return fail(LBM_E_INVAL, "steps per launch must be 1 or 2, not %d", steps_per_launch);
+    if (rows != 0 && rows != 4 && rows != 8) return fail(LBM_E_INVAL, "tile rows %d not one of 4, 8", rows);
+    std::initializer_list<int> cand = rows ? std::initializer_list<int>{rows} : std::initializer_list<int>{8, 4};
+    for (int r : cand) {
+        uint32_t links = 0;
+        if (c->fusion_fits(r, &links)) {
+            c->fuse = 2;
+            c->fuse_rows = r;
+            c->fuse_links = links;
+            return LBM_OK;
+        }
+    }
+    return fail(LBM_E_INVAL, "two-step kernel needs nx %% 64 == 0, ny %% rows == 0 and a tile's wall links in "
+                "LDS (nx %u, ny %u)", c->pr.nx, c->pr.ny);
 }
 
 lbm_status lbm_set_timing(lbm_ctx* c, int32_t on)

@@ -16,6 +16,7 @@ constexpr uint32_t kSolid = 0xFFu;
 // of wall links owned by sites < 64 c.  Links are stored sorted by (site, direction), so the
 // links of a site, of a wavefront and of a block are contiguous index ranges.
 constexpr int kChunk = 64;
+constexpr int kFuseTX = 64;  // tile width of the two-step kernel (one chunk)
 
 // Lattice geometry shared by every kernel.  Population plane i starts at element i * ps, with the
 // plane stride ps = n rounded up to a whole number of 64-site chunks, so that every plane starts on
@@ -145,6 +146,11 @@ hipError_t launch_precompute(const LinkInput& in, const PrecomputeArgs& a, doubl
                              hipStream_t stream);
 // Bytes of LDS one block of `block` threads needs for `max_links` wall links.
 size_t step_lds_bytes(bool fp32, uint32_t max_links);
+// Two steps per launch on 64 x rows tiles (rows: 4 or 8); a.lds_links must hold the wall links of
+// any tile.  Needs nx % 64 == 0 and ny % rows == 0.
+size_t step2_lds_bytes(bool fp32, int rows, uint32_t max_links);
+hipError_t launch_step2_f64(const StepArgs<double>& a, int rows, bool write_u, bool node_diffuse, hipStream_t stream);
+hipError_t launch_step2_f32(const StepArgs<float>& a, int rows, bool write_u, bool node_diffuse, hipStream_t stream);
 hipError_t launch_step_f64(const StepArgs<double>& a, int block, bool write_u, bool node_diffuse,
                            hipStream_t stream);
 hipError_t launch_step_f32(const StepArgs<float>& a, int block, bool write_u, bool node_diffuse,

@@ -170,6 +170,134 @@ __device__ __forceinline__ void macro_fp64(const Pop<T>& p, double rho0, double 
     uy = (jy + 0.5 * rho * ay) / rho;
 }
 
+// Result of one collision: the post-collision deviations h_i = g'_i and the macroscopic values
+// the boundary rule needs.
+template <typename T>
+struct Post {
+    T h0, h1, h2, h3, h4, h5, h6, h7, h8;
+    T dr, rho, ux, uy, u2;
+};
+
+// Collision of one fluid site in moment space (Eqs. (LBEColli), (LBEforce), (MomentPost)) on the
+// deviations g_i = f_i - w_i rho0; shared by every step kernel so that they agree bit for bit.
+template <typename T>
+__device__ __forceinline__ void collide(const Pop<T>& p, const StepArgs<T>& a, Post<T>& o)
+{
+    const T g0 = p.g0, g1 = p.g1, g2 = p.g2, g3 = p.g3, g4 = p.g4, g5 = p.g5, g6 = p.g6, g7 = p.g7, g8 = p.g8;
+    // conserved moments and half-force velocity, Eq. (FluidMacr)
+    const T s14 = (g1 + g2) + (g3 + g4);
+    const T s58 = (g5 + g6) + (g7 + g8);
+    const T dr = g0 + s14 + s58;
+    const T rho = a.rho0 + dr;
+    const T jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
+    const T jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
+    const T irho = T(1) / rho;
+    const T ux = (jx + T(0.5) * rho * a.ax) * irho;
+    const T uy = (jy + T(0.5) * rho * a.ay) * irho;
+    const T u2 = ux * ux + uy * uy;
+
+    // non-conserved moments m = M g (rows of M in Sec. II)
+    const T e = T(-4) * g0 - s14 + T(2) * s58;
+    const T eps = T(4) * g0 - T(2) * s14 + s58;
+    const T qx = T(-2) * (g1 - g3) + ((g5 - g6) + (g8 - g7));
+    const T qy = T(-2) * (g2 - g4) + ((g5 + g6) - (g7 + g8));
+    const T pxx = (g1 + g3) - (g2 + g4);
+    const T pxy = (g5 + g7) - (g6 + g8);
+
+    // equilibria of Eq. (LBEequi) in moment space (deviation from the rest state) and the Guo
+    // forcing moments M Fbar of Eq. (LBEforce): (0, 6 rho u.a, -6 rho u.a, rho a_x, -rho a_x,
+    // rho a_y, -rho a_y, 2 rho (u_x a_x - u_y a_y), rho (u_x a_y + u_y a_x))
+    const T ru2 = T(3) * rho * u2;
+    const T ua6 = T(6) * rho * (ux * a.ax + uy * a.ay);
+    const T ep = e - a.s_e * (e - (T(-2) * dr + ru2)) + a.c_e * ua6;
+    const T epsp = eps - a.s_eps * (eps - (dr - ru2)) - a.c_eps * ua6;
+    const T qxp = qx - a.s_q * (qx + rho * ux) - a.c_q * (rho * a.ax);
+    const T qyp = qy - a.s_q * (qy + rho * uy) - a.c_q * (rho * a.ay);
+    const T pxxp =
+        pxx - a.s_s * (pxx - rho * (ux * ux - uy * uy)) + a.c_s * (T(2) * rho * (ux * a.ax - uy * a.ay));
+    const T pxyp = pxy - a.s_s * (pxy - rho * (ux * uy)) + a.c_s * (rho * (ux * a.ay + uy * a.ax));
+    // conserved: rho' = rho; j' = j + rho a exactly (the tau_j relaxation and forcing cancel)
+    const T jxp = jx + rho * a.ax;
+    const T jyp = jy + rho * a.ay;
+
+    // f' = M^-1 m' with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+    // The conserved moments (rho, j) never relax, so a rounded constant 1/9 or 1/6 would scale
+    // mass and momentum by (1 + its rounding error) at every collision and the bias would grow
+    // over the whole run; they are divided with a two-term constant (error below one ulp,
+    // unbiased).
+    const T r0 = split_mul(dr, Third<T>::c9_hi, Third<T>::c9_lo);
+    const T r1 = ep * T(1.0 / 36.0);
+    const T r2 = epsp * T(1.0 / 36.0);
+    const T r3 = split_mul(jxp, Third<T>::c6_hi, Third<T>::c6_lo);
+    const T r4 = qxp * T(1.0 / 12.0);
+    const T r5 = split_mul(jyp, Third<T>::c6_hi, Third<T>::c6_lo);
+    const T r6 = qyp * T(1.0 / 12.0);
+    const T r7 = pxxp * T(0.25);
+    const T r8 = pxyp * T(0.25);
+    const T A = r0 - r1 - T(2) * r2;
+    const T B = r0 + T(2) * r1 + r2;
+    const T X = r3 - T(2) * r4, Y = r5 - T(2) * r6;
+    const T XD = r3 + r4, YD = r5 + r6;
+    const T h0 = r0 - T(4) * r1 + T(4) * r2;
+    const T h1 = A + X + r7;
+    const T h2 = A + Y - r7;
+    const T h3 = A - X + r7;
+    const T h4 = A - Y - r7;
+    const T h5 = B + XD + YD + r8;
+    const T h6 = B - XD + YD - r8;
+    const T h7 = B - XD - YD + r8;
+    const T h8 = B + XD - YD - r8;
+
+    o.h0 = h0;
+    o.h1 = h1;
+    o.h2 = h2;
+    o.h3 = h3;
+    o.h4 = h4;
+    o.h5 = h5;
+    o.h6 = h6;
+    o.h7 = h7;
+    o.h8 = h8;
+    o.dr = dr;
+    o.rho = rho;
+    o.ux = ux;
+    o.uy = uy;
+    o.u2 = u2;
+}
+
+// Boundary value of Eq. (EqNewBDSC) in deviation form for link k:
+//   g_i(x, t+1) = a1 g_ibar + a2 g'_i + a3 g'_ibar + beta rho + kappa w_i (drho + rho phi_i(u)).
+template <typename T>
+__device__ __forceinline__ T link_value(const LinkCoef<T>& c, uint32_t k, T gb, T hi, T hb, T rho, T wdif)
+{
+    return c.a1[k] * gb + c.a2[k] * hi + c.a3[k] * hb + c.beta[k] * rho + c.kappa[k] * wdif;
+}
+
+// w_i (drho + rho phi_i(u)) (node reading) or w_i drho (wall reading, where the wall equilibrium
+// is folded into beta), phi_i(u) = 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u^2 with cu = c_i.u.
+template <typename T, bool NODE>
+__device__ __forceinline__ T diffuse_term(T w, T dr, T rho, T cu, T u2)
+{
+    T dif = dr;
+    if (NODE) dif += rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * u2);
+    return w * dif;
+}
+
+// Calls fn(d, g_ibar, g'_i, g'_ibar, w_i, c_i.u) for every wall link direction d of a site with flag
+// byte fl (the unknown population is i = opposite(d)).
+template <typename T, typename F>
+__device__ __forceinline__ void for_links(uint32_t fl, const Pop<T>& p, const Post<T>& o, F&& fn)
+{
+    const T w1 = T(1.0 / 9.0), w5 = T(1.0 / 36.0);
+    if (fl & 0x01u) fn(1, p.g1, o.h3, o.h1, w1, -o.ux);          // toward E, unknown W
+    if (fl & 0x02u) fn(2, p.g2, o.h4, o.h2, w1, -o.uy);          // toward N, unknown S
+    if (fl & 0x04u) fn(3, p.g3, o.h1, o.h3, w1, o.ux);           // toward W, unknown E
+    if (fl & 0x08u) fn(4, p.g4, o.h2, o.h4, w1, o.uy);           // toward S, unknown N
+    if (fl & 0x10u) fn(5, p.g5, o.h7, o.h5, w5, -o.ux - o.uy);   // toward NE, unknown SW
+    if (fl & 0x20u) fn(6, p.g6, o.h8, o.h6, w5, o.ux - o.uy);    // toward NW, unknown SE
+    if (fl & 0x40u) fn(7, p.g7, o.h5, o.h7, w5, o.ux + o.uy);    // toward SW, unknown NE
+    if (fl & 0x80u) fn(8, p.g8, o.h6, o.h8, w5, -o.ux + o.uy);   // toward SE, unknown NW
+}
+
 // LDS staging of one link's operands: five arrays of lds_links entries.
 template <typename T>
 struct LinkStage {
@@ -206,9 +334,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
     if (fl != kSolid) {
         const Nbr b = neighbours(s, g.nx, g.ny);
         const Pop<T> p = pull(a.src.pop, a.src.link, ps, s, b, fl, k0);
-        const T g0 = p.g0, g1 = p.g1, g2 = p.g2, g3 = p.g3, g4 = p.g4, g5 = p.g5, g6 = p.g6, g7 = p.g7,
-                g8 = p.g8;
-
         if (WRITE_U) {
             double dr_d, rho_d, ux_d, uy_d;
             macro_fp64(p, static_cast<double>(a.rho0), static_cast<double>(a.ax), static_cast<double>(a.ay),
@@ -217,69 +342,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
             a.uy_out[s] = uy_d;
         }
 
-        // conserved moments and half-force velocity, Eq. (FluidMacr)
-        const T s14 = (g1 + g2) + (g3 + g4);
-        const T s58 = (g5 + g6) + (g7 + g8);
-        const T dr = g0 + s14 + s58;
-        const T rho = a.rho0 + dr;
-        const T jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
-        const T jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
-        const T irho = T(1) / rho;
-        const T ux = (jx + T(0.5) * rho * a.ax) * irho;
-        const T uy = (jy + T(0.5) * rho * a.ay) * irho;
-        const T u2 = ux * ux + uy * uy;
-
-        // non-conserved moments m = M g (rows of M in Sec. II)
-        const T e = T(-4) * g0 - s14 + T(2) * s58;
-        const T eps = T(4) * g0 - T(2) * s14 + s58;
-        const T qx = T(-2) * (g1 - g3) + ((g5 - g6) + (g8 - g7));
-        const T qy = T(-2) * (g2 - g4) + ((g5 + g6) - (g7 + g8));
-        const T pxx = (g1 + g3) - (g2 + g4);
-        const T pxy = (g5 + g7) - (g6 + g8);
-
-        // equilibria of Eq. (LBEequi) in moment space (deviation from the rest state) and the Guo
-        // forcing moments M Fbar of Eq. (LBEforce): (0, 6 rho u.a, -6 rho u.a, rho a_x, -rho a_x,
-        // rho a_y, -rho a_y, 2 rho (u_x a_x - u_y a_y), rho (u_x a_y + u_y a_x))
-        const T ru2 = T(3) * rho * u2;
-        const T ua6 = T(6) * rho * (ux * a.ax + uy * a.ay);
-        const T ep = e - a.s_e * (e - (T(-2) * dr + ru2)) + a.c_e * ua6;
-        const T epsp = eps - a.s_eps * (eps - (dr - ru2)) - a.c_eps * ua6;
-        const T qxp = qx - a.s_q * (qx + rho * ux) - a.c_q * (rho * a.ax);
-        const T qyp = qy - a.s_q * (qy + rho * uy) - a.c_q * (rho * a.ay);
-        const T pxxp =
-            pxx - a.s_s * (pxx - rho * (ux * ux - uy * uy)) + a.c_s * (T(2) * rho * (ux * a.ax - uy * a.ay));
-        const T pxyp = pxy - a.s_s * (pxy - rho * (ux * uy)) + a.c_s * (rho * (ux * a.ay + uy * a.ax));
-        // conserved: rho' = rho; j' = j + rho a exactly (the tau_j relaxation and forcing cancel)
-        const T jxp = jx + rho * a.ax;
-        const T jyp = jy + rho * a.ay;
-
-        // f' = M^-1 m' with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
-        // The conserved moments (rho, j) never relax, so a rounded constant 1/9 or 1/6 would scale
-        // mass and momentum by (1 + its rounding error) at every collision and the bias would grow
-        // over the whole run; they are divided with a two-term constant (error below one ulp,
-        // unbiased).
-        const T r0 = split_mul(dr, Third<T>::c9_hi, Third<T>::c9_lo);
-        const T r1 = ep * T(1.0 / 36.0);
-        const T r2 = epsp * T(1.0 / 36.0);
-        const T r3 = split_mul(jxp, Third<T>::c6_hi, Third<T>::c6_lo);
-        const T r4 = qxp * T(1.0 / 12.0);
-        const T r5 = split_mul(jyp, Third<T>::c6_hi, Third<T>::c6_lo);
-        const T r6 = qyp * T(1.0 / 12.0);
-        const T r7 = pxxp * T(0.25);
-        const T r8 = pxyp * T(0.25);
-        const T A = r0 - r1 - T(2) * r2;
-        const T B = r0 + T(2) * r1 + r2;
-        const T X = r3 - T(2) * r4, Y = r5 - T(2) * r6;
-        const T XD = r3 + r4, YD = r5 + r6;
-        const T h0 = r0 - T(4) * r1 + T(4) * r2;
-        const T h1 = A + X + r7;
-        const T h2 = A + Y - r7;
-        const T h3 = A - X + r7;
-        const T h4 = A - Y - r7;
-        const T h5 = B + XD + YD + r8;
-        const T h6 = B - XD + YD - r8;
-        const T h7 = B - XD - YD + r8;
-        const T h8 = B + XD - YD - r8;
+        Post<T> o;
+        collide(p, a, o);
+        const T dr = o.dr, rho = o.rho, u2 = o.u2;
+        const T h0 = o.h0, h1 = o.h1, h2 = o.h2, h3 = o.h3, h4 = o.h4, h5 = o.h5, h6 = o.h6, h7 = o.h7, h8 = o.h8;
 
         // Post-collision values leave along c_i and are pulled by x + c_i (the ones heading into
         // a wall are stored too, into slots nobody reads, to keep the lines whole).
@@ -296,26 +362,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
 
         if (fl) {
             // operands of Eq. (EqNewBDSC) for each wall link (x, d); the unknown is i = opposite(d)
-            const T w1 = T(1.0 / 9.0), w5 = T(1.0 / 36.0);
             const uint32_t j0 = k0 - kblk;
-            auto deposit = [&](int d, T gb, T hi, T hb, T w, T cu) {
+            for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
                 const uint32_t j = j0 + rank_of(fl, d);
-                T dif = dr;
-                if (NODE) dif += rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * u2);
                 st.gb[j] = gb;
                 st.hi[j] = hi;
                 st.hb[j] = hb;
                 st.rho[j] = rho;
-                st.dif[j] = w * dif;
-            };
-            if (fl & 0x01u) deposit(1, g1, h3, h1, w1, -ux);        // toward E, unknown W
-            if (fl & 0x02u) deposit(2, g2, h4, h2, w1, -uy);        // toward N, unknown S
-            if (fl & 0x04u) deposit(3, g3, h1, h3, w1, ux);         // toward W, unknown E
-            if (fl & 0x08u) deposit(4, g4, h2, h4, w1, uy);         // toward S, unknown N
-            if (fl & 0x10u) deposit(5, g5, h7, h5, w5, -ux - uy);   // toward NE, unknown SW
-            if (fl & 0x20u) deposit(6, g6, h8, h6, w5, ux - uy);    // toward NW, unknown SE
-            if (fl & 0x40u) deposit(7, g7, h5, h7, w5, ux + uy);    // toward SW, unknown NE
-            if (fl & 0x80u) deposit(8, g8, h6, h8, w5, -ux + uy);   // toward SE, unknown NW
+                st.dif[j] = diffuse_term<T, NODE>(w, dr, rho, cu, u2);
+            });
         }
     } else if (store_line && s < g.n) {
         T* __restrict__ dst = a.dst.pop;
@@ -330,8 +385,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
         const LinkCoef<T> c = a.coef;
         for (uint32_t j = threadIdx.x; j < nl_blk; j += BLOCK) {
             const uint32_t k = kblk + j;
-            a.dst.link[k] = c.a1[k] * st.gb[j] + c.a2[k] * st.hi[j] + c.a3[k] * st.hb[j] +
-                            c.beta[k] * st.rho[j] + c.kappa[k] * st.dif[j];
+            a.dst.link[k] = link_value(c, k, st.gb[j], st.hi[j], st.hb[j], st.rho[j], st.dif[j]);
         }
     }
 }
@@ -341,6 +395,187 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     step_tile<T, WRITE_U, NODE, BLOCK>(a, blockIdx.x * BLOCK, lds_raw);
+}
+
+// ------------------------------------------------------- two time steps per launch (fused)
+//
+// Temporal blocking: a block of 64 (TY + 3) threads owns a tile of 64 x TY sites (64 = one chunk).
+// Step 1 runs on the tile and a one-site halo around it, one wave per row and one more wave for
+// the two halo columns: its sites pull from the global planes and link array of time t, collide,
+// and leave their nine post-collision values in LDS; the tile's sites also evaluate their boundary
+// values and leave each in the LDS slot of the solid neighbour x + c_d, which is exactly where
+// step 2 pulls it.  Step 2 runs on the tile only, pulling from LDS, and stores time t + 2 to the
+// global planes (whole lines) and its boundary values to the link array (link-parallel over the
+// tile rows' contiguous link ranges, as in step_tile).  Each site's arithmetic
+// is that of step_tile (same collide / link_value / diffuse_term), so two fused steps give the
+// bits of two single steps.  Needs nx % 64 == 0 and ny % TY == 0.
+
+template <typename T>
+__device__ __forceinline__ void fused_site1(const StepArgs<T>& a, T* F, uint32_t s, uint32_t fl, uint32_t k0,
+                                            int rr, int cc, bool in_tile, int W, int P, bool node)
+{
+    if (fl == kSolid) return;
+    const Geo& g = a.g;
+    const Nbr b = neighbours(s, g.nx, g.ny);
+    const Pop<T> p = pull(a.src.pop, a.src.link, g.ps, s, b, fl, k0);
+    Post<T> o;
+    collide(p, a, o);
+    const int idx = rr * W + cc;
+    F[idx] = o.h0;
+    F[1 * P + idx] = o.h1;
+    F[2 * P + idx] = o.h2;
+    F[3 * P + idx] = o.h3;
+    F[4 * P + idx] = o.h4;
+    F[5 * P + idx] = o.h5;
+    F[6 * P + idx] = o.h6;
+    F[7 * P + idx] = o.h7;
+    F[8 * P + idx] = o.h8;
+    if (in_tile && fl) {
+        for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
+            // c_d and the unknown direction i = opposite(d)
+            const int cx = (d == 1 || d == 5 || d == 8) ? 1 : ((d == 3 || d == 6 || d == 7) ? -1 : 0);
+            const int cy = (d == 2 || d == 5 || d == 6) ? 1 : ((d == 4 || d == 7 || d == 8) ? -1 : 0);
+            const int i = (d <= 4) ? ((d + 1) & 3) + 1 : ((d - 3) & 3) + 5;
+            const T wd = node ? diffuse_term<T, true>(w, o.dr, o.rho, cu, o.u2)
+                              : diffuse_term<T, false>(w, o.dr, o.rho, cu, o.u2);
+            F[i * P + (rr + cy) * W + (cc + cx)] = link_value(a.coef, k0 + rank_of(fl, d), gb, hi, hb, o.rho, wd);
+        });
+    }
+}
+
+// Tile of block b: blocks are dealt round-robin to the eight XCDs (b % 8), so block b is mapped to
+// tile (b % 8) * (ntiles / 8) + b / 8; each XCD then walks its own contiguous run of tiles in
+// row-major order and neighbouring tiles, whose halos overlap, meet in the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles)
+{
+    if (ntiles % 8u != 0u) return b;
+    return (b % 8u) * (ntiles / 8u) + b / 8u;
+}
+
+template <typename T, bool WRITE_U, bool NODE, int TY>
+__global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
+{
+    constexpr int W = kFuseTX + 2, R = TY + 2, P = R * W;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* F = reinterpret_cast<T*>(lds_raw);  // [9][R][W] post-collision values of step 1
+    T* stg = F + 9 * P;                    // [5][lds_links] link operands of step 2
+    const LinkStage<T> st{stg, stg + a.lds_links, stg + 2 * a.lds_links, stg + 3 * a.lds_links,
+                          stg + 4 * a.lds_links};
+    uint32_t* krow = reinterpret_cast<uint32_t*>(stg + 5 * a.lds_links);  // [TY] first link of each row
+    uint32_t* orow = krow + TY;                                            // [TY + 1] stage offsets
+    uint32_t* k0s = orow + TY + 1;                                         // [TY][64]
+    uint8_t* fls = reinterpret_cast<uint8_t*>(k0s + TY * kFuseTX);         // [TY][64]
+
+    const Geo& g = a.g;
+    const uint32_t tiles_x = g.nx / kFuseTX;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t x0 = (tile % tiles_x) * kFuseTX, y0 = (tile / tiles_x) * TY;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+
+    if (tid < TY) {
+        const uint32_t c = ((y0 + tid) * g.nx + x0) / kChunk;
+        const uint32_t kb = static_cast<uint32_t>(g.chunk_base[c]);
+        krow[tid] = kb;
+        orow[tid + 1] = static_cast<uint32_t>(g.chunk_base[c + 1]) - kb;
+    }
+
+    if (wave < R) {
+        // step 1: wave w takes LDS row w (tile row w - 1; rows -1 and TY are the halo rows)
+        const int rr = wave;
+        const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
+        const uint32_t s = y * g.nx + x0 + lane;
+        const SiteLinks sl = site_links(g, s);
+        const bool in_tile = rr >= 1 && rr <= TY;
+        if (in_tile) {
+            k0s[(rr - 1) * kFuseTX + lane] = sl.k0;
+            fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(sl.fl);
+        }
+        fused_site1(a, F, s, sl.fl, sl.k0, rr, lane + 1, in_tile, W, P, NODE);
+    } else if (lane < 2 * R) {
+        // the last wave: halo columns x0 - 1 (last site of its chunk) and x0 + 64 (first of its chunk)
+        const int rr = lane >> 1, side = lane & 1;
+        const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
+        const uint32_t x = side ? ((x0 + kFuseTX == g.nx) ? 0 : x0 + kFuseTX) : (x0 == 0 ? g.nx - 1 : x0 - 1);
+        const uint32_t s = y * g.nx + x;
+        const uint32_t fl = g.flags[s];
+        uint32_t k0 = 0;
+        if (fl != kSolid)
+            k0 = side ? static_cast<uint32_t>(g.chunk_base[s / kChunk])
+                      : static_cast<uint32_t>(g.chunk_base[s / kChunk + 1]) - static_cast<uint32_t>(__popc(fl));
+        fused_site1(a, F, s, fl, k0, rr, side ? W - 1 : 0, false, W, P, NODE);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        orow[0] = 0;
+        for (int r = 0; r < TY; ++r) orow[r + 1] += orow[r];
+    }
+    __syncthreads();
+
+    // step 2: wave r takes tile row r, pulling from LDS
+    if (wave < TY) {
+        const int r = wave;
+        const uint32_t s = (y0 + r) * g.nx + x0 + lane;
+        const uint32_t fl = fls[r * kFuseTX + lane];
+        const bool store_line = line_has(fl != kSolid, sizeof(T));
+        const uint64_t ps = g.ps;
+        if (fl != kSolid) {
+            const int idx = (r + 1) * W + lane + 1;
+            Pop<T> p;
+            p.g0 = F[idx];
+            p.g1 = F[1 * P + idx - 1];      // from (x-1, y)
+            p.g2 = F[2 * P + idx - W];      // from (x, y-1)
+            p.g3 = F[3 * P + idx + 1];      // from (x+1, y)
+            p.g4 = F[4 * P + idx + W];      // from (x, y+1)
+            p.g5 = F[5 * P + idx - W - 1];  // from (x-1, y-1)
+            p.g6 = F[6 * P + idx - W + 1];  // from (x+1, y-1)
+            p.g7 = F[7 * P + idx + W + 1];  // from (x+1, y+1)
+            p.g8 = F[8 * P + idx + W - 1];  // from (x-1, y+1)
+            if (WRITE_U) {
+                double dr_d, rho_d, ux_d, uy_d;
+                macro_fp64(p, static_cast<double>(a.rho0), static_cast<double>(a.ax), static_cast<double>(a.ay),
+                           dr_d, rho_d, ux_d, uy_d);
+                a.ux_out[s] = ux_d;
+                a.uy_out[s] = uy_d;
+            }
+            Post<T> o;
+            collide(p, a, o);
+            T* __restrict__ dst = a.dst.pop;
+            dst[s] = o.h0;
+            dst[1 * ps + s] = o.h1;
+            dst[2 * ps + s] = o.h2;
+            dst[3 * ps + s] = o.h3;
+            dst[4 * ps + s] = o.h4;
+            dst[5 * ps + s] = o.h5;
+            dst[6 * ps + s] = o.h6;
+            dst[7 * ps + s] = o.h7;
+            dst[8 * ps + s] = o.h8;
+            if (fl) {
+                const uint32_t j0 = orow[r] + (k0s[r * kFuseTX + lane] - krow[r]);
+                for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
+                    const uint32_t j = j0 + rank_of(fl, d);
+                    st.gb[j] = gb;
+                    st.hi[j] = hi;
+                    st.hb[j] = hb;
+                    st.rho[j] = o.rho;
+                    st.dif[j] = diffuse_term<T, NODE>(w, o.dr, o.rho, cu, o.u2);
+                });
+            }
+        } else if (store_line) {
+            T* __restrict__ dst = a.dst.pop;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[i * ps + s] = T(0);
+        }
+    }
+    __syncthreads();
+    // the tile's boundary values, link-parallel over its rows' contiguous link ranges (coalesced)
+    const uint32_t total = orow[TY];
+    const LinkCoef<T> c = a.coef;
+    for (uint32_t jj = tid; jj < total; jj += 64 * (TY + 3)) {
+        int r = 0;
+        while (jj >= orow[r + 1]) ++r;
+        const uint32_t k = krow[r] + (jj - orow[r]);
+        a.dst.link[k] = link_value(c, k, st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
+    }
 }
 
 // View of instance `in` of a batch: its flags, chunk offsets and u record start at its site offset
@@ -776,6 +1011,49 @@ hipError_t launch_residual_batch_f32(const BatchReduceArgs<float>& a, int block,
 }
 
 size_t step_lds_bytes(bool fp32, uint32_t max_links) { return 5 * (fp32 ? 4 : 8) * size_t(max_links); }
+
+size_t step2_lds_bytes(bool fp32, int rows, uint32_t max_links)
+{
+    const size_t t = fp32 ? 4 : 8;
+    return t * (9 * size_t(rows + 2) * (kFuseTX + 2) + 5 * size_t(max_links)) + 4 * size_t(2 * rows + 1) +
+           5 * size_t(rows) * kFuseTX;
+}
+
+namespace {
+
+template <typename T, int TY>
+hipError_t launch_step2_rows(const StepArgs<T>& a, bool write_u, bool node, hipStream_t stream)
+{
+    const uint32_t grid = (a.g.nx / kFuseTX) * (a.g.ny / TY);
+    const size_t lds = step2_lds_bytes(sizeof(T) == 4, TY, a.lds_links);
+    const dim3 block(64 * (TY + 3));
+    if (write_u) {
+        if (node)
+            hipLaunchKernelGGL((k_step2<T, true, true, TY>), dim3(grid), block, lds, stream, a);
+        else
+            hipLaunchKernelGGL((k_step2<T, true, false, TY>), dim3(grid), block, lds, stream, a);
+    } else {
+        if (node)
+            hipLaunchKernelGGL((k_step2<T, false, true, TY>), dim3(grid), block, lds, stream, a);
+        else
+            hipLaunchKernelGGL((k_step2<T, false, false, TY>), dim3(grid), block, lds, stream, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step2_f64(const StepArgs<double>& a, int rows, bool write_u, bool node, hipStream_t stream)
+{
+    return rows == 4 ? launch_step2_rows<double, 4>(a, write_u, node, stream)
+                     : launch_step2_rows<double, 8>(a, write_u, node, stream);
+}
+
+hipError_t launch_step2_f32(const StepArgs<float>& a, int rows, bool write_u, bool node, hipStream_t stream)
+{
+    return rows == 4 ? launch_step2_rows<float, 4>(a, write_u, node, stream)
+                     : launch_step2_rows<float, 8>(a, write_u, node, stream);
+}
 
 hipError_t launch_step_f64(const StepArgs<double>& a, int block, bool write_u, bool node, hipStream_t stream)
 {

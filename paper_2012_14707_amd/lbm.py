@@ -52,7 +52,7 @@ class Info(C.Structure):
                 ("L1", C.c_double), ("L2", C.c_double), ("nu", C.c_double),
                 ("n_sites", C.c_int64), ("n_fluid", C.c_int64), ("n_links", C.c_int64),
                 ("n_clamped", C.c_int32), ("n_nonconvex", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32), ("bytes_per_step", C.c_int64), ("steps", C.c_int64)]
+                ("steps_per_launch", C.c_int32), ("bytes_per_step", C.c_int64), ("steps", C.c_int64)]
 
 
 class BatchLaunch(C.Structure):
@@ -88,6 +88,7 @@ SIGNATURES = {
     "lbm_synchronize": (C.c_int32, [_VP]),
     "lbm_set_launch": (C.c_int32, [_VP, C.c_int32]),
     "lbm_set_timing": (C.c_int32, [_VP, C.c_int32]),
+    "lbm_set_fusion": (C.c_int32, [_VP, C.c_int32, C.c_int32]),
     "lbm_last_step_ms": (C.c_int32, [_VP, _DPTR, C.POINTER(C.c_int64)]),
     "lbm_batch_create": (C.c_int32, [C.c_int32, C.POINTER(Params), C.POINTER(_VP), C.POINTER(_VP),
                                      C.POINTER(C.c_int64), _VP, C.POINTER(_VP)]),
@@ -276,6 +277,10 @@ class Lattice:
 
     def set_launch(self, block=256):
         _check(self._lib.lbm_set_launch(self._h, int(block)))
+
+    def set_fusion(self, steps_per_launch=2, rows=0):
+        """1: one step per kernel launch; 2: two steps per launch (temporal blocking)."""
+        _check(self._lib.lbm_set_fusion(self._h, int(steps_per_launch), int(rows)))
 
     def set_timing(self, on=True):
         _check(self._lib.lbm_set_timing(self._h, int(bool(on))))

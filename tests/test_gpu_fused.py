@@ -1,0 +1,93 @@
+"""Two time steps per launch (temporal blocking, lbm_set_fusion): bit-identical to one step per
+launch on lattices that tile into 64 x rows blocks, for both storage precisions, every tile-row
+option, odd step counts (pairs plus a single step) and moving walls; lattices that do not tile
+keep one step per launch."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2012_14707_amd import geometry as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(case):
+    if case == "cylinders256":
+        return G.random_cylinders(n=256, porosity=0.7, rmin=8, rmax=24, seed=11, kn=0.05, h=32.0, ax=1e-6)
+    if case == "cylinders128x192":
+        return G.random_cylinders(n=128, ny=192, porosity=0.75, rmin=5, rmax=14, seed=4, kn=0.02, h=20.0, ax=2e-6)
+    if case == "channel64":
+        return G.channel(30, nx=64, gamma=0.37, kn=0.05, ax=1e-6, u_top=0.01)
+    if case == "annulus128":
+        return G.annulus(128, 20.0, 50.0, (63.5, 63.5), u_inner=0.01, u_outer=-0.004, kn=0.05)
+    raise KeyError(case)
+
+
+def _fields(shape, seed):
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    y, x = np.mgrid[0:ny, 0:nx]
+    ph = rng.random(3) * 2 * np.pi
+    rho = 1.0 + 0.01 * np.sin(2 * np.pi * x / nx + ph[0])
+    ux = 1e-3 * np.cos(2 * np.pi * 2 * y / ny + ph[1])
+    uy = 5e-4 * np.sin(2 * np.pi * 3 * x / nx + ph[2])
+    return rho, ux, uy
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a.moments_host(), b.moments_host()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["cylinders256", "cylinders128x192", "channel64", "annulus128"])
+def test_two_step_launch_bitwise(case, precision):
+    from paper_2012_14707_amd import lbm
+    pb = _problem(case)
+    fused = lbm.Lattice(pb, precision=precision)
+    single = lbm.Lattice(pb, precision=precision)
+    # default: two steps per launch for fp64 storage where the lattice tiles, one for fp32
+    assert fused.info["steps_per_launch"] == (2 if precision == "fp64" else 1)
+    fused.set_fusion(2)
+    assert fused.info["steps_per_launch"] == 2
+    single.set_fusion(1)
+    assert single.info["steps_per_launch"] == 1
+    init = _fields(pb["solid"].shape, 3)
+    for lat in (fused, single):
+        lat.init_fields(*init)
+    done = 0
+    for rows in (8, 4):
+        fused.set_fusion(2, rows)
+        for n in (37, 2, 1, 60):
+            fused.step(n)
+            single.step(n)
+            done += n
+            assert _same(fused, single), (case, precision, rows, n)
+            assert fused.residual() == single.residual()
+    _say(f"[fused] {case} {precision}: {done} steps bitwise equal, residual {single.residual()[0]:.3e}")
+    assert fused.info["steps"] == single.info["steps"] == done
+
+
+def test_lattices_that_do_not_tile_keep_single_steps():
+    from paper_2012_14707_amd import lbm
+    lat = lbm.Lattice(G.poiseuille_config1(), precision="fp64")
+    assert lat.info["steps_per_launch"] == 1
+    with pytest.raises(lbm.LbmError):
+        lat.set_fusion(2)
+    lat2 = lbm.Lattice(_problem("cylinders256"), precision="fp32")
+    with pytest.raises(lbm.LbmError):
+        lat2.set_fusion(2, 16)  # tiles have 4 or 8 rows
+    with pytest.raises(lbm.LbmError):
+        lat2.set_fusion(3)
