@@ -118,6 +118,24 @@ const char *lbm_last_error(void);
  * LBM_DIFFUSE_NODE, LBM_FP64, a = 0, rho0 = 1, non-periodic. */
 lbm_status lbm_params_default(lbm_params *p);
 
+/* Boundary schemes the paper compares against (Sec. III.B, Sec. IV), as parameter sets of the same
+ * boundary rule Eq. (EqNewBDSC). */
+enum {
+    LBM_SCHEME_PRESENT = 0,     /* l of Eq. (Eqexlva), r of Eq. (NSliCoertsr), uniform tau_q of
+                                   Eq. (NSliCoertstq): the paper's prescription (the defaults) */
+    LBM_SCHEME_PREVIOUS = 1,    /* l = 0 ("previous" curved scheme): r of Eq. (SliCoeffrtsrD) and tau_q of
+                                   Eq. (SliCoeffrtstqrD) evaluated at one frozen gamma */
+    LBM_SCHEME_HALFWAY_DBB = 2  /* halfway diffuse bounce-back: l = 0, r of Eq. (SliCoeffHar), tau_q of
+                                   Eq. (SliCoeffHata); the caller also gives q = 1/2 on every link */
+};
+
+/* Sets the mode fields and the tau_q override of *p for one of the compared schemes: reads kn, h,
+ * sigma, L1, L2 and tau_s_override of *p (derived as in lbm_create when unset) and writes l_mode,
+ * r_mode and tau_q_override.  gamma_frozen: the gamma in (0, 1] at which LBM_SCHEME_PREVIOUS
+ * evaluates Eq. (SliCoeffrtstqrD) (ignored otherwise).  LBM_E_PARAM if the resulting tau_q is not
+ * above 1/2; no device work. */
+lbm_status lbm_params_comparison(lbm_params *p, int32_t scheme, double gamma_frozen);
+
 /* Creates a lattice (Sec. III.A problem statement).
  *   solid    host, uint8 [ny * nx] row-major, nonzero = solid (closed set: nodes on a wall are solid)
  *   links    host, n_links records; every (fluid node, direction) whose neighbour is solid must

@@ -233,3 +233,45 @@ lbm_status precompute_links(const Prepared& pr, double* coef64, float* coef32, i
 }
 
 }  // namespace lbm
+
+extern "C" lbm_status lbm_params_comparison(lbm_params* p, int32_t scheme, double gamma_frozen)
+{
+    if (!p) return lbm::fail(LBM_E_INVAL, "null params");
+    const double sq = std::sqrt(6.0 / lbm::kPi);
+    const double ts = lbm::is_set(p->tau_s_override) ? p->tau_s_override : 0.5 + sq * p->kn * p->h;  // Eq. (tKnrela)
+    if (!(ts > 0.5)) return lbm::fail(LBM_E_PARAM, "tau_s = %g must exceed 1/2", ts);
+    const double L1 = std::isnan(p->L1) ? (2.0 - p->sigma) * (1.0 - 0.1817 * p->sigma) / p->sigma : p->L1;
+    const double L2 = std::isnan(p->L2) ? 1.0 / lbm::kPi + 0.5 * L1 * L1 : p->L2;
+    const double t2 = 2.0 * ts - 1.0;
+    const double den = 4.0 * t2 * (2.0 * sq * ts + L1 * t2);
+    double tq = 0.0;
+    switch (scheme) {
+    case LBM_SCHEME_PRESENT:
+        p->l_mode = LBM_L_PAPER;
+        p->r_mode = LBM_R_FROM_LEFF;
+        p->tau_q_override = 0.0;
+        return LBM_OK;
+    case LBM_SCHEME_PREVIOUS: {
+        if (!(gamma_frozen > 0.0 && gamma_frozen <= 1.0))
+            return lbm::fail(LBM_E_INVAL, "frozen gamma %g outside (0, 1]", gamma_frozen);
+        const double g = gamma_frozen;
+        // Eq. (SliCoeffrtstqrD)
+        tq = (L1 * t2 * (2.0 * ts * (6.0 * g - 1.0) + 1.0) +
+              sq * ts * (L2 * lbm::kPi * t2 * t2 + 12.0 * g * g + 2.0 * t2 * (6.0 * g - 1.0))) /
+             den;
+        break;
+    }
+    case LBM_SCHEME_HALFWAY_DBB:
+        // Eq. (SliCoeffHata)
+        tq = (L1 * t2 * (4.0 * ts + 1.0) + sq * ts * (L2 * lbm::kPi * t2 * t2 + 4.0 * t2 + 3.0)) / den;
+        break;
+    default:
+        return lbm::fail(LBM_E_INVAL, "unknown scheme %d", scheme);
+    }
+    if (!(tq > 0.5)) return lbm::fail(LBM_E_PARAM, "tau_q = %g must exceed 1/2", tq);
+    // l = 0; r = Eq. (SliCoeffrtsr) at l = 0, which is Eq. (SliCoeffrtsrD) = Eq. (SliCoeffHar)
+    p->l_mode = LBM_L_ZERO;
+    p->r_mode = LBM_R_FROM_LEFF;
+    p->tau_q_override = tq;
+    return LBM_OK;
+}

@@ -120,6 +120,66 @@ def poiseuille_config1():
     return channel(20, nx=4, gamma=0.3, kn=0.1, ax=1e-6)
 
 
+# ----------------------------------------------------------------------- inclined walls
+
+def inclined_channel(tan_theta, nx=120, n_ab=16, kn=0.0194, a=1e-6, ny=None, offset=0.3, **kw):
+    """Poiseuille channel whose flat walls are inclined at angle theta to the lattice (Sec.
+    IV.A.2, Fig. ScheInPois), driven by a body force a along the walls.
+
+    The lattice is doubly periodic and holds a family of identical parallel channels: with
+    v = y - x tan(theta) - offset taken modulo ny, fluid is 0 < v < n_ab (n_ab = the vertical
+    extent of the channel, the paper's segment AB) and the rest is solid.  nx tan(theta) must be a
+    multiple of ny, so that x -> x + nx maps the walls onto themselves; ny defaults to the smallest
+    such value that leaves more than 1 + tan(theta) solid rows between channels (so that no link
+    of length <= sqrt 2 meets two walls).  Every link's gamma is the exact crossing of the link with
+    the wall line.  Perpendicular width H = n_ab cos(theta); the node's distance from the lower
+    wall is v cos(theta).  The default offset keeps every node off the walls."""
+    t = float(tan_theta)
+    rise = nx * t
+    if abs(rise - round(rise)) > 1e-9:
+        raise ValueError("nx tan(theta) must be an integer")
+    rise = int(round(rise))
+    if ny is None:
+        cands = [d for d in range(1, rise + 1) if rise % d == 0 and d - n_ab > 1.0 + t]
+        if not cands:
+            raise ValueError("no period leaves enough solid rows")
+        ny = min(cands)
+    if rise % ny or ny - n_ab <= 1.0 + t:
+        raise ValueError(f"ny = {ny} incompatible with nx tan(theta) = {rise} and n_ab = {n_ab}")
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    v = np.mod(yy - xx * t - offset, ny)
+    fluid = (v > 0.0) & (v < n_ab)
+    solid = (~fluid).astype(np.uint8)
+    xs, ys, ds = wall_candidates(solid, 1, 1)
+    # v along the link x_f + s c_d, s in [0, 1], without wrapping (it stays within one period)
+    v0 = np.mod(ys - xs * t - offset, ny)
+    dv = CY[ds] - CX[ds] * t
+    v1 = v0 + dv
+    lower = v1 <= 0.0
+    upper = v1 >= n_ab
+    if not np.all(lower ^ upper):
+        raise AssertionError("every link must cross exactly one wall")
+    q = np.where(lower, (0.0 - v0) / dv, (n_ab - v0) / dv)
+    links = dict(x=xs, y=ys, dir=ds, q=q, ubx=np.zeros(len(xs)), uby=np.zeros(len(xs)))
+    cos = 1.0 / math.sqrt(1.0 + t * t)
+    h = n_ab * cos
+    params = base_params(periodic_x=1, periodic_y=1, kn=kn, h=h, ax=a * cos, ay=a * t * cos)
+    params.update(kw)
+    meta = dict(kind="inclined", tan_theta=t, H=h, n_ab=n_ab, a=a, offset=offset,
+                yprime=np.where(fluid, v * cos, np.nan))
+    return dict(params=params, solid=solid, links=links, meta=meta)
+
+
+def inclined_profile(problem, L1, L2, nu):
+    """Analytic velocity along the walls at every fluid node (Sec. IV.A.2):
+    u_c [4 (y'/H)(1 - y'/H) + 4 L1 Kn + 8 L2 Kn^2], u_c = a H^2 / (8 nu); NaN on solid nodes."""
+    m = problem["meta"]
+    h, kn = m["H"], problem["params"]["kn"]
+    yp = m["yprime"]
+    uc = m["a"] * h * h / (8.0 * nu)
+    return uc * (4.0 * yp / h * (1.0 - yp / h) + 4.0 * L1 * kn + 8.0 * L2 * kn * kn), uc
+
+
 # ----------------------------------------------------------------------- circular walls
 
 def annulus(n=132, r1=32.0, r2=64.0, center=None, u_inner=0.01, u_outer=0.0, kn=0.01, **kw):

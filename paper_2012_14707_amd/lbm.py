@@ -75,6 +75,7 @@ SIGNATURES = {
     "lbm_version": (C.c_int32, []),
     "lbm_last_error": (C.c_char_p, []),
     "lbm_params_default": (C.c_int32, [C.POINTER(Params)]),
+    "lbm_params_comparison": (C.c_int32, [C.POINTER(Params), C.c_int32, C.c_double]),
     "lbm_create": (C.c_int32, [C.POINTER(Params), _VP, C.POINTER(Link), C.c_int64, _VP, C.POINTER(_VP)]),
     "lbm_destroy": (C.c_int32, [_VP]),
     "lbm_get_info": (C.c_int32, [_VP, C.POINTER(Info)]),
@@ -169,6 +170,25 @@ def make_params(params, shape, precision="fp64"):
             setattr(p, name, v)
     p.precision = PRECISION[precision]
     return p
+
+
+SCHEMES = {"present": 0, "previous": 1, "halfway_dbb": 2}
+_L_NAMES = {v: k for k, v in L_MODES.items()}
+_R_NAMES = {v: k for k, v in R_MODES.items()}
+
+
+def comparison_problem(problem, scheme, gamma_frozen=0.5):
+    """A copy of a problem set up for one of the compared boundary schemes (lbm_params_comparison);
+    for the halfway DBB scheme every link's q becomes 1/2."""
+    lib = load()
+    p = make_params(problem["params"], np.asarray(problem["solid"]).shape)
+    _check(lib.lbm_params_comparison(C.byref(p), SCHEMES[scheme], float(gamma_frozen)))
+    params = dict(problem["params"], l_mode=_L_NAMES[p.l_mode], r_mode=_R_NAMES[p.r_mode],
+                  tau_q_override=p.tau_q_override)
+    links = dict(problem["links"])
+    if scheme == "halfway_dbb":
+        links["q"] = np.full(len(links["q"]), 0.5)
+    return dict(problem, params=params, links=links)
 
 
 def make_links(links):

@@ -174,3 +174,29 @@ def test_batch_validation_errors():
     assert st == -4 and not h.value and msg.startswith("instance 1")
     assert lib.lbm_batch_destroy(None) == 0
     assert lib.lbm_batch_step(None, 1) == -1
+
+
+def test_params_comparison_matches_the_paper_formulas():
+    """lbm_params_comparison (host only) against the formulas typed from the paper in the tests."""
+    from tests import paper_formulas as P
+    lib = lbm.load()
+    pb = G.inclined_channel(1.2)
+    ts = P.tau_s_of_kn(pb["params"]["kn"], pb["params"]["h"])
+    L1 = P.l1_poiseuille(1.0)
+    L2 = P.l2_poiseuille(L1)
+    for scheme, g, want in ((1, 0.3, P.tau_q_slicoeffrtstq(0.3, 0.0, ts, L1, L2)), (1, 0.5, P.tau_q_halfway(ts, L1, L2)),
+                            (2, 0.0, P.tau_q_halfway(ts, L1, L2))):
+        p = lbm.make_params(pb["params"], pb["solid"].shape)
+        assert lib.lbm_params_comparison(C.byref(p), scheme, g) == 0
+        assert p.l_mode == lbm.L_MODES["zero"] and p.r_mode == lbm.R_MODES["from_leff"]
+        assert p.tau_q_override == pytest.approx(want, rel=1e-13)
+    p = lbm.make_params(pb["params"], pb["solid"].shape)
+    assert lib.lbm_params_comparison(C.byref(p), 0, 0.0) == 0
+    assert p.l_mode == lbm.L_MODES["paper"] and p.tau_q_override == 0.0
+    assert lib.lbm_params_comparison(C.byref(p), 1, 1.5) == -1
+    assert lib.lbm_params_comparison(C.byref(p), 7, 0.5) == -1
+    assert lib.lbm_params_comparison(None, 0, 0.5) == -1
+    # the halfway problem copy puts every link at q = 1/2 and leaves the original alone
+    q0 = pb["links"]["q"].copy()
+    hb = lbm.comparison_problem(pb, "halfway_dbb")
+    assert np.all(hb["links"]["q"] == 0.5) and np.array_equal(pb["links"]["q"], q0)

@@ -109,3 +109,29 @@ def test_unpadded_mask_rejected():
     s[2, 2] = 1
     with pytest.raises(ValueError):
         G.wall_candidates(s, 0, 0)
+
+
+@pytest.mark.parametrize("tan_theta", [0.2, 1.2, 2.0])
+def test_inclined_channel_links_cross_the_walls(tan_theta):
+    pb = G.inclined_channel(tan_theta)
+    ny, nx = pb["solid"].shape
+    assert (nx * tan_theta) % ny == pytest.approx(0.0, abs=1e-9) or (nx * tan_theta) % ny == pytest.approx(ny)
+    L = pb["links"]
+    t, off, nab = tan_theta, pb["meta"]["offset"], pb["meta"]["n_ab"]
+    cx, cy = G.CX[L["dir"]], G.CY[L["dir"]]
+    # the crossing point x_f + q c_d lies on a wall line (v = 0 or v = n_ab, v = y - x tan - offset)
+    v = L["y"] + L["q"] * cy - (L["x"] + L["q"] * cx) * t - off
+    vm = np.mod(v + 0.5, ny) - 0.5
+    on_wall = np.minimum(np.abs(vm), np.abs(vm - nab))
+    assert on_wall.max() < 1e-9
+    assert np.all((L["q"] > 0) & (L["q"] <= 1))
+    # x_f fluid, x_f + c_d solid (with the periodic wrap), every such pair exactly once
+    s = pb["solid"]
+    assert np.all(s[L["y"], L["x"]] == 0)
+    assert np.all(s[(L["y"] + cy) % ny, (L["x"] + cx) % nx] == 1)
+    xs, ys, ds = G.wall_candidates(s, 1, 1)
+    assert len(xs) == len(L["x"])
+    # the mask is periodic with the walls: shifting x by nx maps v onto itself modulo ny
+    assert pb["meta"]["H"] == pytest.approx(nab / np.sqrt(1 + t * t))
+    a = np.hypot(pb["params"]["ax"], pb["params"]["ay"])
+    assert a == pytest.approx(pb["meta"]["a"]) and pb["params"]["ay"] / pb["params"]["ax"] == pytest.approx(t)
