@@ -67,68 +67,105 @@ __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, i
 
 // out[p][co] = act(bias[co] + sum_{tap, ci} x[p + off(tap)][ci] w[tap][co][ci]), with zero padding
 // or periodic wrap-around at the image edges.
-// One block computes a 64-pixel x 64-channel tile; each of its four waves a 32 x 32 quarter with
-// four 16x16x32 MFMAs per 32-deep K step.  K runs over (tap, ci); Cin is a multiple of 8 so every
-// 8-wide K group lies in one tap and is one 16-byte load.
-template <int TAPS>
+// One block of four waves computes a BM-pixel x BN-channel tile (the launcher picks the largest of
+// 256 x 32, 128 x 64, 64 x 64, 64 x 32 that still gives enough blocks to fill the chip); the waves
+// form a WGM x WGN grid and each multiplies a (BM / WGM) x (BN / WGN) part with 16x16x32 MFMAs.  K runs over (tap, ci);
+// Cin is a multiple of 8 so every 8-wide K group lies in one tap and is one 16-byte load.  The
+// next K step's operands are loaded into registers while the current one is multiplied, and LDS
+// is double-buffered, so there is one barrier per K step.
+template <int TAPS, int BM, int BN>
 __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
 {
-    __shared__ __align__(16) bf16 As[TM * LDK];
-    __shared__ __align__(16) bf16 Bs[TN * LDK];
+    constexpr int WGN = BN >= 64 ? 2 : 1, WGM = 4 / WGN;         // wave grid
+    constexpr int MI = BM / WGM / 16, NJ = BN / WGN / 16;         // MFMA tiles per wave
+    constexpr int AR = BM / 64;            // A rows loaded per thread per K step
+    constexpr int BR = (BN * 4 + 255) / 256;  // B rows per thread (1; threads beyond BN * 4 idle)
+    __shared__ __align__(16) bf16 As[2][BM * LDK];
+    __shared__ __align__(16) bf16 Bs[2][BN * LDK];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int P = a.N * a.H * a.W;
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     const int K = TAPS * a.Cin;
-    const int lm = tid / 4, lg = tid % 4;  // tile row loaded by this thread, 8-wide K group
-    const int p = m0 + lm;
-    int pn = 0, py = 0, px = 0;
-    if (p < P) decompose(p, a.H, a.W, pn, py, px);
-    const int co_l = n0 + lm;
-    f4 acc[2][2];
+    const int lg = tid % 4;  // 8-wide K group loaded by this thread
+    int pn[AR], py[AR], px[AR];
+    bool pin[AR];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
-    for (int k0 = 0; k0 < K; k0 += TK) {
+    for (int j = 0; j < AR; ++j) {
+        const int p = m0 + tid / 4 + 64 * j;
+        pin[j] = p < P;
+        pn[j] = py[j] = px[j] = 0;
+        if (pin[j]) decompose(p, a.H, a.W, pn[j], py[j], px[j]);
+    }
+    const int co_l = n0 + tid / 4;
+    const bool b_thread = BR * 256 > tid && tid / 4 < BN;
+
+    bf16x8 ra[AR], rb;
+    auto load = [&](int k0) {
         const int k = k0 + lg * 8;
-        bf16x8 va = {}, vb = {};
-        if (k < K) {
-            const int tap = k / a.Cin, ci = k - tap * a.Cin;
-            if (p < P) {
-                int yy = py + (TAPS == 9 ? tap / 3 - 1 : 0), xx = px + (TAPS == 9 ? tap % 3 - 1 : 0);
+        const bool kin = k < K;
+        const int tap = kin ? k / a.Cin : 0, ci = kin ? k - tap * a.Cin : 0;
+        const int dy = (TAPS == 9 ? tap / 3 - 1 : 0), dx = (TAPS == 9 ? tap % 3 - 1 : 0);
+#pragma unroll
+        for (int j = 0; j < AR; ++j) {
+            ra[j] = bf16x8{};
+            if (kin && pin[j]) {
+                int yy = py[j] + dy, xx = px[j] + dx;
                 if (a.periodic) {
                     yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
                     xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
                 }
                 if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    va = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((pn * a.H + yy) * a.W + xx) * a.x.cs +
-                                                          a.x.co + ci);
+                    ra[j] = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((pn[j] * a.H + yy) * a.W + xx) * a.x.cs +
+                                                             a.x.co + ci);
             }
-            if (co_l < a.Cout)
-                vb = *reinterpret_cast<const bf16x8*>(a.w + (size_t(tap) * a.Cout + co_l) * a.Cin + ci);
         }
-        *reinterpret_cast<bf16x8*>(As + lm * LDK + lg * 8) = va;
-        *reinterpret_cast<bf16x8*>(Bs + lm * LDK + lg * 8) = vb;
-        __syncthreads();
+        rb = bf16x8{};
+        if (b_thread && kin && co_l < a.Cout)
+            rb = *reinterpret_cast<const bf16x8*>(a.w + (size_t(tap) * a.Cout + co_l) * a.Cin + ci);
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < AR; ++j)
+            *reinterpret_cast<bf16x8*>(&As[buf][(tid / 4 + 64 * j) * LDK + lg * 8]) = ra[j];
+        if (b_thread) *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * LDK + lg * 8]) = rb;
+    };
+
+    f4 acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int wm = (wave / WGN) * (BM / WGM), wn = (wave % WGN) * (BN / WGN);
+
+    load(0);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        const bool more = k0 + TK < K;
+        if (more) load(k0 + TK);
         // A operand: lane holds row lane % 16, k = 8 (lane / 16) .. +7; B likewise by column
+        bf16x8 fb[NJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + lane % 16) * LDK + 8 * (lane / 16));
+        for (int j = 0; j < NJ; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn + 16 * j + lane % 16) * LDK + 8 * (lane / 16)]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 fb =
-                    *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + lane % 16) * LDK + 8 * (lane / 16));
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
-            }
+        for (int i = 0; i < MI; ++i) {
+            const bf16x8 fa =
+                *reinterpret_cast<const bf16x8*>(&As[buf][(wm + 16 * i + lane % 16) * LDK + 8 * (lane / 16)]);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
         }
+        if (more) stash(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
     // result: lane holds column lane % 16, rows 4 (lane / 16) + r
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             const int col = n0 + wn + 16 * j + lane % 16;
             if (col >= a.Cout) continue;
             const float b = a.bias ? a.bias[col] : 0.f;
@@ -542,12 +579,22 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
                         int Cout, int taps, bool relu, bool periodic, hipStream_t st)
 {
     ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0};
-    const int P = N * H * W;
-    const dim3 grid((P + TM - 1) / TM, (Cout + TN - 1) / TN);
-    if (taps == 9)
-        hipLaunchKernelGGL(k_conv_fwd<9>, grid, dim3(256), 0, st, a);
+    const long P = long(N) * H * W;
+    // the largest tile that still leaves about four blocks per compute unit (256 CUs)
+    auto blocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
+    auto go = [&](auto kern, int bm, int bn) {
+        const dim3 grid(unsigned((P + bm - 1) / bm), unsigned((Cout + bn - 1) / bn));
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a);
+    };
+    const bool t9 = taps == 9;
+    if (Cout >= 64 && blocks(128, 64) >= 1024)
+        t9 ? go(k_conv_fwd<9, 128, 64>, 128, 64) : go(k_conv_fwd<1, 128, 64>, 128, 64);
+    else if (Cout >= 64)
+        t9 ? go(k_conv_fwd<9, 64, 64>, 64, 64) : go(k_conv_fwd<1, 64, 64>, 64, 64);
+    else if (blocks(256, 32) >= 1024)
+        t9 ? go(k_conv_fwd<9, 256, 32>, 256, 32) : go(k_conv_fwd<1, 256, 32>, 256, 32);
     else
-        hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, st, a);
+        t9 ? go(k_conv_fwd<9, 64, 32>, 64, 32) : go(k_conv_fwd<1, 64, 32>, 64, 32);
     return hipGetLastError();
 }
 
