@@ -46,13 +46,23 @@ enum {
     LBM_L_TWO_GAMMA = 4,         /* l = 2 gamma */
     LBM_L_GAMMA2 = 5,            /* l = gamma^2 */
     LBM_L_GAMMA2_PLUS_GAMMA = 6, /* l = gamma^2 + gamma */
-    LBM_L_FIXED = 7              /* l = l_override on every link */
+    LBM_L_FIXED = 7,             /* l = l_override on every link */
+    LBM_L_WALL_FIT = 8           /* wall reading (LBM_DIFFUSE_WALL): l such that the Kn^2 term of the
+                                    scheme's Poiseuille slip equals 8 L2 Kn^2 of Eq. (PhyscPoiSlip) with
+                                    the uniform tau_q; requires LBM_R_WALL_FIT.  The near-wall relation
+                                    of Eq. (NumerSana) under that reading keeps B of Eq. (CoeC) and has
+                                    A = [(1+l)(1-r)(tau_s+1) + 2r(1+gamma)] / Den; along the curve of
+                                    LBM_R_WALL_FIT, B is affine in 1 + l, which gives l in closed form */
 };
 /* Combination parameter r of Eq. (EqNewBDSC). */
 enum {
     LBM_R_FROM_LEFF = 0, /* Eq. (SliCoeffrtsr) at the l actually used; equals Eq. (NSliCoertsr) where l is not clamped */
     LBM_R_PAPER = 1,     /* Eq. (NSliCoertsr) as printed, also on clamped links */
-    LBM_R_FIXED = 2      /* r = r_override on every link */
+    LBM_R_FIXED = 2,     /* r = r_override on every link */
+    LBM_R_WALL_FIT = 3   /* wall reading: r such that the Kn term of the slip equals 4 L1 Kn, i.e.
+                            r / (1 - r) = (1 + l)(tau_s - gamma - L1 lambda) / (2 L1 lambda) with
+                            lambda = Kn H of Eq. (tKnrela).  Exists only for gamma < tau_s - L1 lambda
+                            and L1 > 0: lbm_create fails with LBM_E_PARAM on any other link */
 };
 /* Velocity of the Maxwell-diffuse equilibrium f_i^eq(rho_f, .) in Eq. (EqNewBDSC). */
 enum {
@@ -125,13 +135,16 @@ enum {
                                    Eq. (NSliCoertstq): the paper's prescription (the defaults) */
     LBM_SCHEME_PREVIOUS = 1,    /* l = 0 ("previous" curved scheme): r of Eq. (SliCoeffrtsrD) and tau_q of
                                    Eq. (SliCoeffrtstqrD) evaluated at one frozen gamma */
-    LBM_SCHEME_HALFWAY_DBB = 2  /* halfway diffuse bounce-back: l = 0, r of Eq. (SliCoeffHar), tau_q of
+    LBM_SCHEME_HALFWAY_DBB = 2, /* halfway diffuse bounce-back: l = 0, r of Eq. (SliCoeffHar), tau_q of
                                    Eq. (SliCoeffHata); the caller also gives q = 1/2 on every link */
+    LBM_SCHEME_WALL_READING = 3 /* the present scheme re-derived for the literal reading of the diffuse
+                                   part: LBM_DIFFUSE_WALL, LBM_L_WALL_FIT, LBM_R_WALL_FIT and the uniform
+                                   tau_q of Eq. (NSliCoertstq) */
 };
 
 /* Sets the mode fields and the tau_q override of *p for one of the compared schemes: reads kn, h,
  * sigma, L1, L2 and tau_s_override of *p (derived as in lbm_create when unset) and writes l_mode,
- * r_mode and tau_q_override.  gamma_frozen: the gamma in (0, 1] at which LBM_SCHEME_PREVIOUS
+ * r_mode and tau_q_override (LBM_SCHEME_WALL_READING also sets diffuse).  gamma_frozen: the gamma in (0, 1] at which LBM_SCHEME_PREVIOUS
  * evaluates Eq. (SliCoeffrtstqrD) (ignored otherwise).  LBM_E_PARAM if the resulting tau_q is not
  * above 1/2; no device work. */
 lbm_status lbm_params_comparison(lbm_params *p, int32_t scheme, double gamma_frozen);

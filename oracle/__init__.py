@@ -17,8 +17,8 @@ import numpy as np
 from . import build as _build
 
 _L_MODES = {"paper": 0, "clamp_neg": 1, "zero": 2, "gamma": 3, "two_gamma": 4, "gamma2": 5,
-            "gamma2_plus_gamma": 6, "fixed": 7}
-_R_MODES = {"from_leff": 0, "paper": 1, "fixed": 2}
+            "gamma2_plus_gamma": 6, "fixed": 7, "wall_fit": 8}
+_R_MODES = {"from_leff": 0, "paper": 1, "fixed": 2, "wall_fit": 3}
 _DIFFUSE = {"node": 0, "wall": 1}
 _BC = {"new": 0, "dbb": 1}
 

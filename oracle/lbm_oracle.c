@@ -22,6 +22,9 @@
  *     Eqs. (SliCoeffrtsr)/(NSliCoertsr) for r, Eq. (NSliCoertstq) for the uniform tau_q,
  *     Eq. (EqECond) for the upper bound on E, and the clamp l := 0 when l < -0.4 (end of
  *     Sec. III.B).
+ *   - for the literal (wall-velocity) reading of the diffuse part, the same prescription route
+ *     repeated with that reading: r and l per link from matching the Kn and Kn^2 terms of the
+ *     scheme's Poiseuille slip to Eq. (PhyscPoiSlip), solved by bisection.
  *
  * Precision: every lattice quantity is held in x87 extended precision (long double, 64-bit
  * significand), i.e. at least fp64.  Populations are O(1) while the slip-flow velocities of
@@ -85,8 +88,8 @@ enum { ORA_OK = 0, ORA_E_INVAL = -1, ORA_E_NOMEM = -2, ORA_E_GEOMETRY = -4, ORA_
 
 /* Modes.  These integers are the oracle's own; callers map their names onto them. */
 enum { L_PAPER = 0, L_CLAMP_NEG = 1, L_ZERO = 2, L_GAMMA = 3, L_TWO_GAMMA = 4, L_GAMMA2 = 5,
-       L_GAMMA2_PLUS_GAMMA = 6, L_FIXED = 7 };
-enum { R_FROM_LEFF = 0, R_PAPER = 1, R_FIXED = 2 };
+       L_GAMMA2_PLUS_GAMMA = 6, L_FIXED = 7, L_WALL_FIT = 8 };
+enum { R_FROM_LEFF = 0, R_PAPER = 1, R_FIXED = 2, R_WALL_FIT = 3 };
 enum { DIFFUSE_NODE = 0, DIFFUSE_WALL = 1 };
 enum { BC_NEW = 0, BC_DBB = 1 };
 
@@ -218,10 +221,119 @@ static int derive_globals(const ora_params *p, real *ts, real *L1, real *L2, rea
     return ORA_OK;
 }
 
-/* Per-link l and r under the selected modes. */
-static void derive_link(const ora_params *p, real g, real ts, real L1, real E, real *l_raw, real *l_eff, real *r)
+/* ---- wall reading: the diffuse equilibrium of Eq. (EqNewBDSC) taken at the wall velocity.
+ *
+ * Repeating the analysis of Sec. III.B with f^eq(rho, u_w) in the rule changes only the first
+ * coefficient of the steady near-wall relation u_1 = A u_0 + B a + C u_w, Eq. (NumerSana):
+ *   A = [(1+l)(1-r)(tau_s+1) + 2r(1+gamma)] / Den,  Den = (1+l)(1-r) tau_s + 2 r gamma,
+ * C = 1 - A, and B stays as printed in Eq. (CoeC).  The parameters are then fixed as the paper
+ * fixes them for its own reading: substitute the Poiseuille profile, Eq. (OrSnumve), with
+ * y_0 = gamma and y_1 = 1 + gamma (dx = 1, u_w = 0), so that the scheme's slip U_s(H) is a sum of
+ * a 1/H and a 1/H^2 term; with Kn H = lambda = (tau_s - 1/2)/sqrt(6/pi), Eq. (tKnrela), match the
+ * 1/H term to 4 L1 Kn and the 1/H^2 term to 8 L2 Kn^2 of Eq. (PhyscPoiSlip).  The two conditions
+ * are solved here by bisection: r from the first at a given l, then l from the second. */
+
+/* A of the near-wall relation under the wall reading. */
+static real wall_A(real r, real l, real g, real ts)
 {
-    real lr;
+    real den = (1.0L + l) * (1.0L - r) * ts + 2.0L * r * g;
+    return ((1.0L + l) * (1.0L - r) * (ts + 1.0L) + 2.0L * r * (1.0L + g)) / den;
+}
+
+/* B of Eq. (CoeC). */
+static real coe_B(real r, real l, real g, real ts, real tq)
+{
+    real den = (1.0L + l) * (1.0L - r) * ts + 2.0L * r * g;
+    real num = (1.0L + r + l - l * r) * (1.0L + 4.0L * tq - 8.0L * ts - 8.0L * tq * ts)
+             + 12.0L * r * ((2.0L * g - l) * (2.0L * ts - 1.0L) + (1.0L - 2.0L * g) * ts);
+    return num / (2.0L * den * (2.0L * ts - 1.0L));
+}
+
+/* With u_0 = p(gamma) + u_s and u_1 = p(1 + gamma) + u_s, p(y) = (a / 2 nu) y (H - y), the relation
+ * u_1 = A u_0 + B a gives u_s (1 - A) = B a - p(1 + gamma) + A p(gamma), and with u_c = a H^2 / 8 nu
+ * U_s = u_s / u_c = s1 / H + s2 / H^2.  These are s1 and s2. */
+static void wall_slip_terms(real r, real l, real g, real ts, real tq, real *s1, real *s2)
+{
+    real A = wall_A(r, l, g, ts), B = coe_B(r, l, g, ts, tq), nu = (ts - 0.5L) / 3.0L;
+    *s1 = -4.0L * ((1.0L + g) - A * g) / (1.0L - A);
+    *s2 = (8.0L * nu * B + 4.0L * ((1.0L + g) * (1.0L + g) - A * g * g)) / (1.0L - A);
+}
+
+/* Bisection for a sign change of f on [lo, hi] (f(lo) and f(hi) of opposite sign). */
+typedef real (*scalar_fn)(real x, const real *ctx);
+static real bisect(scalar_fn f, const real *ctx, real lo, real hi)
+{
+    real flo = f(lo, ctx);
+    for (int it = 0; it < 200; ++it) {
+        real mid = 0.5L * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        real fm = f(mid, ctx);
+        if ((fm < 0.0L) == (flo < 0.0L)) { lo = mid; flo = fm; } else hi = mid;
+    }
+    return 0.5L * (lo + hi);
+}
+
+/* ctx = {l, gamma, tau_s, tau_q, lambda, L1, L2} */
+static real first_order_gap(real r, const real *c)
+{
+    real s1, s2;
+    wall_slip_terms(r, c[0], c[1], c[2], c[3], &s1, &s2);
+    return s1 - 4.0L * c[5] * c[4];
+}
+
+/* r in [0, 1] meeting the first-order condition at l; -1 if no r there does. */
+static real wall_r(const real *c)
+{
+    /* r = 1 is bounce-back (no slip at all, s1 = 0); r -> 0 is the diffuse limit with the
+     * largest slip, s1 = 4 (tau_s - gamma).  The target 4 L1 lambda must lie in between. */
+    real lo = 1e-30L, hi = 1.0L;
+    real flo = first_order_gap(lo, c), fhi = first_order_gap(hi, c);
+    if (!(flo > 0.0L && fhi < 0.0L)) return -1.0L;
+    return bisect(first_order_gap, c, lo, hi);
+}
+
+static real second_order_gap(real l, const real *c0)
+{
+    real c[7];
+    for (int i = 0; i < 7; ++i) c[i] = c0[i];
+    c[0] = l;
+    real r = wall_r(c);
+    real s1, s2;
+    wall_slip_terms(r, l, c[1], c[2], c[3], &s1, &s2);
+    return s2 - 8.0L * c[6] * c[4] * c[4];
+}
+
+/* (l, r) of the wall reading for one link; ORA_E_PARAM where no admissible pair exists. */
+static int wall_fit(real g, real ts, real tq, real L1, real L2, real *l_out, real *r_out)
+{
+    real lam = (ts - 0.5L) / sq6pi();
+    real c[7] = {0.0L, g, ts, tq, lam, L1, L2};
+    if (wall_r(c) < 0.0L) return ORA_E_PARAM;
+    /* l > -1 (the rule divides by 1 + l); widen the upper end until the gap changes sign. */
+    real lo = -1.0L + 1e-12L, hi = 1.0L;
+    real flo = second_order_gap(lo, c);
+    while ((second_order_gap(hi, c) < 0.0L) == (flo < 0.0L)) {
+        hi *= 2.0L;
+        if (hi > 1e8L) return ORA_E_PARAM;
+    }
+    real l = bisect(second_order_gap, c, lo, hi);
+    c[0] = l;
+    *l_out = l;
+    *r_out = wall_r(c);
+    return ORA_OK;
+}
+
+/* Per-link l and r under the selected modes. */
+static int derive_link(const ora_params *p, real g, real ts, real tq, real L1, real L2, real E, real *l_raw,
+                       real *l_eff, real *r)
+{
+    real lr = 0.0L;
+    if (p->l_mode == L_WALL_FIT) {
+        if (p->r_mode != R_WALL_FIT) return ORA_E_INVAL;
+        int st = wall_fit(g, ts, tq, L1, L2, &lr, r);
+        *l_raw = *l_eff = lr;
+        return st;
+    }
     switch (p->l_mode) {
     case L_ZERO: lr = 0.0L; break;
     case L_GAMMA: lr = g; break;
@@ -238,7 +350,12 @@ static void derive_link(const ora_params *p, real g, real ts, real L1, real E, r
     *l_eff = le;
     if (p->r_mode == R_FIXED) *r = p->r_override;
     else if (p->r_mode == R_PAPER) *r = r_of_gamma(g, ts, L1, E);
-    else *r = r_of_l(le, ts, L1);
+    else if (p->r_mode == R_WALL_FIT) {
+        real c[7] = {le, g, ts, tq, (ts - 0.5L) / sq6pi(), L1, L2};
+        *r = wall_r(c);
+        if (*r < 0.0L) return ORA_E_PARAM;
+    } else *r = r_of_l(le, ts, L1);
+    return ORA_OK;
 }
 
 /* Exported precompute: globals plus, per link, (l_raw, l_eff, r). */
@@ -252,7 +369,8 @@ int ora_derive(const ora_params *p, int64_t nlinks, const double *q, ora_globals
     if (st != ORA_OK) return st;
     for (int64_t k = 0; k < nlinks; ++k) {
         real lr, le, r, g = q[k];
-        derive_link(p, g, ts, L1, E, &lr, &le, &r);
+        int lst = derive_link(p, g, ts, tq, L1, L2, E, &lr, &le, &r);
+        if (lst != ORA_OK) return lst;
         if (le != lr) out->n_clamped++;
         real lo = 2.0L * g - 1.0L; if (lo < 0.0L) lo = 0.0L;
         if (le < lo || le > 2.0L * g) out->n_nonconvex++;
@@ -446,7 +564,8 @@ int ora_create(const ora_params *p, const uint8_t *solid, int64_t nlinks, const 
         if (o->linkidx[s * 9 + d] >= 0) { ora_destroy(o); return ORA_E_GEOMETRY; }
         o->linkidx[s * 9 + d] = (int32_t)k;
         real lr, le, r;
-        derive_link(p, q[k], ts, L1, E, &lr, &le, &r);
+        int lst = derive_link(p, q[k], ts, tq, L1, L2, E, &lr, &le, &r);
+        if (lst != ORA_OK) { ora_destroy(o); return lst; }
         if (le != lr) g->n_clamped++;
         real lo = 2.0L * q[k] - 1.0L; if (lo < 0.0L) lo = 0.0L;
         if (le < lo || le > 2.0L * q[k]) g->n_nonconvex++;

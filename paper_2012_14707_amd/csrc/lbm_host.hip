@@ -68,9 +68,11 @@ lbm_status prepare(const lbm_params* p, const uint8_t* solid, const lbm_link* li
     const uint64_t n64 = uint64_t(p->nx) * uint64_t(p->ny);
     if (n64 >= (uint64_t(1) << 31))
         return fail(LBM_E_INVAL, "lattice of %llu sites exceeds 2^31", (unsigned long long)n64);
-    if (p->l_mode < 0 || p->l_mode > 7 || p->r_mode < 0 || p->r_mode > 2 || p->diffuse < 0 || p->diffuse > 1 ||
-        p->precision < 0 || p->precision > 1)
+    if (p->l_mode < 0 || p->l_mode > LBM_L_WALL_FIT || p->r_mode < 0 || p->r_mode > LBM_R_WALL_FIT ||
+        p->diffuse < 0 || p->diffuse > 1 || p->precision < 0 || p->precision > 1)
         return fail(LBM_E_INVAL, "mode out of range");
+    if (p->l_mode == LBM_L_WALL_FIT && p->r_mode != LBM_R_WALL_FIT)
+        return fail(LBM_E_INVAL, "LBM_L_WALL_FIT needs LBM_R_WALL_FIT");
     if (!(p->rho0 > 0.0) || !std::isfinite(p->ax) || !std::isfinite(p->ay))
         return fail(LBM_E_PARAM, "rho0 must be positive and a finite");
     out.p = *p;
@@ -201,7 +203,9 @@ lbm_status precompute_links(const Prepared& pr, double* coef64, float* coef32, i
         LinkInput in{d_q, d_ubx, d_uby, d_dir};
         PrecomputeArgs a{};
         a.tau_s = pr.g.tau_s;
+        a.tau_q = pr.g.tau_q;
         a.L1 = pr.g.L1;
+        a.L2 = pr.g.L2;
         a.E = pr.g.E;
         a.sq6pi = std::sqrt(6.0 / kPi);
         a.r_override = pr.p.r_override;
@@ -220,8 +224,16 @@ lbm_status precompute_links(const Prepared& pr, double* coef64, float* coef32, i
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
     cleanup();
     if (he != hipSuccess) return fail(LBM_E_HIP, "link upload or precompute failed: %s", hipGetErrorString(he));
+    const bool wall_fit = pr.p.l_mode == LBM_L_WALL_FIT || pr.p.r_mode == LBM_R_WALL_FIT;
+    const double lam = (pr.g.tau_s - 0.5) / std::sqrt(6.0 / kPi);
+    if (wall_fit && !(pr.g.L1 > 0.0)) return fail(LBM_E_PARAM, "the wall-reading fit needs L1 > 0");
     for (size_t k = 0; k < nl; ++k) {
         const double lraw = lrow[k], l = lrow[nl + k], r = lrow[2 * nl + k];
+        if (wall_fit && !(pr.q[k] < pr.g.tau_s - pr.g.L1 * lam))
+            return fail(LBM_E_PARAM,
+                        "link %lld: gamma = %g: the wall reading reaches the Kn term of the slip only for "
+                        "gamma < tau_s - L1 Kn H = %g",
+                        (long long)pr.order[k], pr.q[k], pr.g.tau_s - pr.g.L1 * lam);
         if (!(1.0 + l > 0.0) || !(r >= 0.0 && r <= 1.0))
             return fail(LBM_E_PARAM, "link %lld: l = %g, r = %g outside 1 + l > 0, 0 <= r <= 1",
                         (long long)pr.order[k], l, r);
@@ -261,6 +273,12 @@ extern "C" lbm_status lbm_params_comparison(lbm_params* p, int32_t scheme, doubl
              den;
         break;
     }
+    case LBM_SCHEME_WALL_READING:
+        p->l_mode = LBM_L_WALL_FIT;
+        p->r_mode = LBM_R_WALL_FIT;
+        p->diffuse = LBM_DIFFUSE_WALL;
+        p->tau_q_override = 0.0;
+        return LBM_OK;
     case LBM_SCHEME_HALFWAY_DBB:
         // Eq. (SliCoeffHata)
         tq = (L1 * t2 * (4.0 * ts + 1.0) + sq * ts * (L2 * lbm::kPi * t2 * t2 + 4.0 * t2 + 3.0)) / den;

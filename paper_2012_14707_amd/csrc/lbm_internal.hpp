@@ -124,7 +124,7 @@ struct LinkInput {
 
 // Global parameters of the prescription needed by the per-link precompute.
 struct PrecomputeArgs {
-    double tau_s, L1, E, sq6pi;
+    double tau_s, tau_q, L1, L2, E, sq6pi;
     double r_override, l_override;
     int32_t l_mode, r_mode, diffuse;
     int64_t n_links;

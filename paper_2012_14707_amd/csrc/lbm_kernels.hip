@@ -627,8 +627,8 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const BatchArgs<T> b)
 
 __device__ __forceinline__ double weight_of(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
-// Coefficients of Eq. (EqNewBDSC) per link from gamma, the l and r rules of Sec. III.B and the
-// wall velocity; one thread per link, fp64.  Output rows of coef64 (n_links each):
+// Coefficients of Eq. (EqNewBDSC) per link from gamma, the l and r rules of Sec. III.B (or their
+// counterparts under the wall reading) and the wall velocity; one thread per link, fp64.  Output rows of coef64 (n_links each):
 // l_raw, l_eff, r, alpha1, alpha2, alpha3, beta, kappa.
 __global__ void __launch_bounds__(256) k_precompute(const LinkInput in, const PrecomputeArgs a, double* coef64,
                                                     float* coef32)
@@ -639,6 +639,15 @@ __global__ void __launch_bounds__(256) k_precompute(const LinkInput in, const Pr
     const double g = in.q[k];
     const double ts = a.tau_s, L1 = a.L1, E = a.E, sq = a.sq6pi;
     const double t2 = 2.0 * ts - 1.0;
+    // Wall reading (diffuse equilibrium at the wall velocity): the near-wall relation of
+    // Eq. (NumerSana) keeps B of Eq. (CoeC) but has A = [(1+l)(1-r)(tau_s+1) + 2r(1+gamma)] / Den.
+    // Matching the Kn term of the Poiseuille slip to Eq. (PhyscPoiSlip) (lambda = Kn H from
+    // Eq. (tKnrela)) fixes A = (1 + gamma + L1 lambda) / (gamma + L1 lambda), i.e.
+    // r / (1 - r) = (1 + l) k with k = (tau_s - gamma - L1 lambda) / (2 L1 lambda); along that
+    // curve B is affine in 1 + l, B = B0 - 6 k (1 + l) / (tau_s + 2 k gamma), so matching the Kn^2
+    // term (B = Bt) gives 1 + l in closed form.  k <= 0 has no admissible r (NaN, rejected).
+    const double lam = (ts - 0.5) / sq;
+    const double kw = (ts - g - L1 * lam) / (2.0 * L1 * lam);
     double l_raw;
     switch (a.l_mode) {
     case 2: l_raw = 0.0; break;
@@ -647,6 +656,17 @@ __global__ void __launch_bounds__(256) k_precompute(const LinkInput in, const Pr
     case 5: l_raw = g * g; break;
     case 6: l_raw = g * g + g; break;
     case 7: l_raw = a.l_override; break;
+    case 8: {
+        const double tq = a.tau_q, nu = (ts - 0.5) / 3.0;
+        const double at = (1.0 + g + L1 * lam) / (g + L1 * lam);
+        const double bt = ((1.0 - at) * 2.0 * a.L2 * lam * lam + at * g * g - (1.0 + g) * (1.0 + g)) / (2.0 * nu);
+        const double dd = ts + 2.0 * kw * g;
+        const double b0 = ((1.0 + 2.0 * kw) * (1.0 + 4.0 * tq - 8.0 * ts - 8.0 * tq * ts) +
+                           12.0 * kw * ((2.0 * g + 1.0) * t2 + (1.0 - 2.0 * g) * ts)) /
+                          (2.0 * dd * t2);
+        l_raw = kw > 0.0 ? (b0 - bt) * dd / (6.0 * kw) - 1.0 : __builtin_nan("");
+        break;
+    }
     default: l_raw = (sq * g * g + g * t2 * (L1 + sq)) / (sq * t2) + E; break;  // Eq. (Eqexlva)
     }
     double l = l_raw;
@@ -655,6 +675,9 @@ __global__ void __launch_bounds__(256) k_precompute(const LinkInput in, const Pr
     double r;
     if (a.r_mode == 2) {
         r = a.r_override;
+    } else if (a.r_mode == 3) {  // wall reading: A of the near-wall relation at the l used
+        const double x = (1.0 + l) * kw;
+        r = kw > 0.0 ? x / (1.0 + x) : __builtin_nan("");
     } else if (a.r_mode == 1) {  // Eq. (NSliCoertsr)
         const double br = g * g + g * t2 + (1.0 + E) * t2;
         r = (L1 * ts * g * t2 + sq * ts * br) / (L1 * t2 * ((2.0 + g) * ts - 1.0) + sq * ts * br);

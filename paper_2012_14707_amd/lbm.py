@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "liblbm.so")
 
 L_MODES = {"paper": 0, "clamp_neg": 1, "zero": 2, "gamma": 3, "two_gamma": 4, "gamma2": 5,
-           "gamma2_plus_gamma": 6, "fixed": 7}
-R_MODES = {"from_leff": 0, "paper": 1, "fixed": 2}
+           "gamma2_plus_gamma": 6, "fixed": 7, "wall_fit": 8}
+R_MODES = {"from_leff": 0, "paper": 1, "fixed": 2, "wall_fit": 3}
 DIFFUSE = {"node": 0, "wall": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 
@@ -172,9 +172,10 @@ def make_params(params, shape, precision="fp64"):
     return p
 
 
-SCHEMES = {"present": 0, "previous": 1, "halfway_dbb": 2}
+SCHEMES = {"present": 0, "previous": 1, "halfway_dbb": 2, "wall_reading": 3}
 _L_NAMES = {v: k for k, v in L_MODES.items()}
 _R_NAMES = {v: k for k, v in R_MODES.items()}
+_DIFFUSE_NAMES = {v: k for k, v in DIFFUSE.items()}
 
 
 def comparison_problem(problem, scheme, gamma_frozen=0.5):
@@ -184,7 +185,7 @@ def comparison_problem(problem, scheme, gamma_frozen=0.5):
     p = make_params(problem["params"], np.asarray(problem["solid"]).shape)
     _check(lib.lbm_params_comparison(C.byref(p), SCHEMES[scheme], float(gamma_frozen)))
     params = dict(problem["params"], l_mode=_L_NAMES[p.l_mode], r_mode=_R_NAMES[p.r_mode],
-                  tau_q_override=p.tau_q_override)
+                  diffuse=_DIFFUSE_NAMES[p.diffuse], tau_q_override=p.tau_q_override)
     links = dict(problem["links"])
     if scheme == "halfway_dbb":
         links["q"] = np.full(len(links["q"]), 0.5)

@@ -193,6 +193,12 @@ def test_params_comparison_matches_the_paper_formulas():
     p = lbm.make_params(pb["params"], pb["solid"].shape)
     assert lib.lbm_params_comparison(C.byref(p), 0, 0.0) == 0
     assert p.l_mode == lbm.L_MODES["paper"] and p.tau_q_override == 0.0
+    assert lib.lbm_params_comparison(C.byref(p), 3, 0.0) == 0
+    assert (p.l_mode, p.r_mode, p.diffuse) == (lbm.L_MODES["wall_fit"], lbm.R_MODES["wall_fit"],
+                                               lbm.DIFFUSE["wall"])
+    assert p.tau_q_override == 0.0
+    wb = lbm.comparison_problem(pb, "wall_reading")
+    assert (wb["params"]["l_mode"], wb["params"]["r_mode"], wb["params"]["diffuse"]) == ("wall_fit",) * 2 + ("wall",)
     assert lib.lbm_params_comparison(C.byref(p), 1, 1.5) == -1
     assert lib.lbm_params_comparison(C.byref(p), 7, 0.5) == -1
     assert lib.lbm_params_comparison(None, 0, 0.5) == -1

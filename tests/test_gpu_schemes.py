@@ -92,3 +92,75 @@ def test_inclined_steady_profile_and_ordering(tan_theta):
              f"{err[name]:.4f}")
     assert err["present"] < 0.04
     assert err["present"] < err["previous"] < err["halfway_dbb"]
+
+
+# ------------------------------------------------- wall reading with re-derived parameters
+
+def test_wall_reading_link_coefficients():
+    """The wall-reading fit's per-link (l, r) (closed form, fp64 on the device) against the
+    oracle's bisection on the two slip conditions, over the curved walls of the annulus at Kn = 0.05
+    (every gamma admissible), and the rejection of inadmissible links at Kn = 0.0194."""
+    from paper_2012_14707_amd import lbm
+    pb = G.couette_config2(0.05)
+    gpb = lbm.comparison_problem(pb, "wall_reading")
+    lat = lbm.Lattice(gpb, precision="fp64")
+    c = lat.link_coeffs()
+    _, lk = oracle.derive(dict(pb["params"], l_mode="wall_fit", r_mode="wall_fit", diffuse="wall"), pb["links"]["q"])
+    _say(f"[wall fit] {len(lk)} links, l in [{lk[:, 1].min():.3f}, {lk[:, 1].max():.3f}], "
+         f"r in [{lk[:, 2].min():.3f}, {lk[:, 2].max():.3f}]")
+    np.testing.assert_allclose(c[:, 0], lk[:, 0], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(c[:, 1], lk[:, 1], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(c[:, 2], lk[:, 2], rtol=1e-11, atol=1e-12)
+    assert lat.info["n_clamped"] == 0
+    lat.close()
+    bad = lbm.comparison_problem(G.inclined_channel(0.2), "wall_reading")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Lattice(bad, precision="fp64")
+    assert e.value.status == -5 and "tau_s - L1 Kn H" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Lattice(dict(gpb, params=dict(gpb["params"], r_mode="from_leff")), precision="fp64")
+    assert e.value.status == -1
+
+
+def test_wall_reading_config1_parity_and_profile():
+    """Config 1 under the wall reading with the re-derived parameters: fp64 and fp32 parity with the
+    oracle after 300 steps, and the fp64 steady state on the analytic profile of Eq. (numvelo)."""
+    from paper_2012_14707_amd import lbm
+    pb = G.poiseuille_config1()
+    gpb = lbm.comparison_problem(pb, "wall_reading")
+    ora = oracle.Oracle(dict(pb["params"], l_mode="wall_fit", r_mode="wall_fit", diffuse="wall"),
+                        pb["solid"], pb["links"])
+    ora.step(300)
+    for precision, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        lat = lbm.Lattice(gpb, precision=precision)
+        lat.step(300)
+        err = _rel(lat.moments_host(), ora.moments(), pb["solid"])
+        _say(f"[wall fit] config 1 {precision}: rel error vs oracle {err:.2e}")
+        assert err <= tol, (precision, err)
+        lat.close()
+    lat = lbm.Lattice(gpb, precision="fp64")
+    steps, res = lat.run_to_steady(1e-13, 100, 50_000)
+    _, ux, _ = lat.moments_host()
+    g = lat.info
+    h = pb["meta"]["H"]
+    uc = 1e-6 * h * h / (8 * g["nu"])
+    U = P.poiseuille_profile(pb["meta"]["y"], h, g["L1"], g["L2"], 0.1)
+    e = np.max(np.abs(ux[1:-1, :] / uc - U[:, None])) / U.max()
+    _say(f"[wall fit] config 1 steady after {steps} steps (residual {res:.1e}): max rel error vs Eq. (numvelo) {e:.2e}")
+    assert e < 1e-9
+
+
+def test_wall_reading_couette_parity():
+    """Moving curved walls (annulus, Kn = 0.05) under the wall reading with the re-derived
+    parameters: fp64 parity with the oracle after 200 steps."""
+    from paper_2012_14707_amd import lbm
+    pb = G.couette_config2(0.05)
+    gpb = lbm.comparison_problem(pb, "wall_reading")
+    ora = oracle.Oracle(dict(pb["params"], l_mode="wall_fit", r_mode="wall_fit", diffuse="wall"),
+                        pb["solid"], pb["links"])
+    ora.step(200)
+    lat = lbm.Lattice(gpb, precision="fp64")
+    lat.step(200)
+    err = _rel(lat.moments_host(), ora.moments(), pb["solid"])
+    _say(f"[wall fit] annulus Kn 0.05 fp64: rel error vs oracle {err:.2e}")
+    assert err <= 1e-12

@@ -386,3 +386,124 @@ def test_inclined_channel_scheme_ordering(tan_theta):
     e = _inclined_errors(tan_theta)
     assert e["present"] < 0.04, e
     assert e["present"] < e["previous"] < e["dbb"], e
+
+
+# ------------------------------------------------- wall reading with re-derived parameters
+
+WALL_FIT = dict(l_mode="wall_fit", r_mode="wall_fit", diffuse="wall")
+
+
+def _profile_relation_gap(r, l, g, ts, tq, L1, L2, lam, h, a=1e-6):
+    """u_1 - A u_0 - B a for the analytic Poiseuille profile of Eq. (OrSnumve) with the slip of
+    Eq. (PhyscPoiSlip) (Kn = lambda / H), at y_0 = gamma and y_1 = 1 + gamma, with the near-wall
+    coefficients of the wall reading (A re-derived, B of Eq. (CoeC)); relative to u_c."""
+    nu = (ts - 0.5) / 3
+    uc = a * h * h / (8 * nu)
+    us = uc * P.slip_physical(L1, L2, lam / h)
+    u0 = 4 * uc * g / h * (1 - g / h) + us
+    u1 = 4 * uc * (1 + g) / h * (1 - (1 + g) / h) + us
+    A = P.near_wall_A_wall_reading(r, l, g, ts)
+    B = P.near_wall_coeffs(r, l, g, ts, tq)[1]
+    return (u1 - A * u0 - B * a) / uc
+
+
+@pytest.mark.parametrize("kn,h", [(0.1, 19.6), (0.05, 32.0), (0.0194, 15.7)])
+def test_wall_fit_satisfies_the_profile_at_every_height(kn, h):
+    """With the diffuse equilibrium at the wall velocity, the (r, l) the oracle solves for make the
+    steady near-wall relation (re-derived A, printed B of Eq. (CoeC)) hold exactly for the analytic
+    slip profile, at any channel height with Kn H fixed: both the Kn and the Kn^2 term of
+    Eq. (PhyscPoiSlip) are met.  Checked here by substituting the profile, not through the
+    oracle's own slip terms."""
+    L1 = P.l1_poiseuille(1.0)
+    L2 = P.l2_poiseuille(L1)
+    ts = P.tau_s_of_kn(kn, h)
+    lam = kn * h
+    gammas = [g for g in (0.05, 0.2, 0.35, 0.5, 0.6, 0.8, 1.0) if g < ts - L1 * lam - 1e-3]
+    assert len(gammas) >= 4
+    params = dict(kn=kn, h=h, **WALL_FIT)
+    glob, lk = oracle.derive(params, np.array(gammas))
+    for g, (l_raw, l, r) in zip(gammas, lk):
+        assert l_raw == l and 0.0 < r < 1.0 and 1.0 + l > 0.0
+        for hh in (h, 2.7 * h, 0.4 * h):
+            gap = _profile_relation_gap(r, l, g, glob["tau_s"], glob["tau_q"], L1, L2, lam, hh)
+            assert abs(gap) < 1e-12, (g, hh, gap)
+        # the node reading's parameters do not satisfy the wall reading's relation
+        rn = P.r_slicoeffrtsr(l, glob["tau_s"], L1)
+        assert abs(_profile_relation_gap(rn, l, g, glob["tau_s"], glob["tau_q"], L1, L2, lam, h)) > 1e-3
+
+
+def test_wall_fit_r_meets_the_first_order_term_at_any_l():
+    """r_mode wall_fit with another l rule: the Kn term is met, so the profile's relation gap, in
+    units of a dt, no longer depends on the channel height (the Kn^2 mismatch left is a constant)."""
+    L1 = P.l1_poiseuille(1.0)
+    L2 = P.l2_poiseuille(L1)
+    kn, h = 0.1, 19.6
+    ts = P.tau_s_of_kn(kn, h)
+    for l_mode in ("zero", "gamma", "paper"):
+        glob, lk = oracle.derive(dict(kn=kn, h=h, l_mode=l_mode, r_mode="wall_fit", diffuse="wall"),
+                                 np.array([0.3, 0.7]))
+        for g, (_, l, r) in zip((0.3, 0.7), lk):
+            gaps = [_profile_relation_gap(r, l, g, ts, glob["tau_q"], L1, L2, kn * h, hh) * hh * hh
+                    for hh in (h, 3 * h, 0.5 * h)]
+            assert max(gaps) - min(gaps) < 1e-9, (l_mode, g, gaps)
+            if l_mode != "paper":
+                assert abs(gaps[0]) > 1e-3  # the second-order term is not met
+
+
+def test_wall_fit_limit():
+    """The diffuse limit r -> 0 gives the largest first-order slip the rule can make, 4 (tau_s -
+    gamma) / H; the fit therefore exists only for gamma < tau_s - L1 Kn H.  Kn = 0.0194, H = 15.7 puts
+    that bound at about 0.67."""
+    kn, h = 0.0194, 15.7
+    L1 = P.l1_poiseuille(1.0)
+    bound = P.tau_s_of_kn(kn, h) - L1 * kn * h
+    assert 0.6 < bound < 0.7
+    oracle.derive(dict(kn=kn, h=h, **WALL_FIT), np.array([bound - 1e-6]))
+    with pytest.raises(oracle.OracleError):
+        oracle.derive(dict(kn=kn, h=h, **WALL_FIT), np.array([bound + 1e-6]))
+    with pytest.raises(oracle.OracleError):  # the l rule needs its r rule
+        oracle.derive(dict(kn=kn, h=h, l_mode="wall_fit", diffuse="wall"), np.array([0.3]))
+
+
+def test_wall_fit_config1_analytic_profile():
+    """Config 1 under the literal reading (diffuse equilibrium at the wall velocity) with the
+    re-derived (r, l) reaches the analytic slip profile of Eq. (numvelo), as the paper's
+    prescription does under the node reading; the same (r, l) under the node reading do not."""
+    pb = G.poiseuille_config1()
+    h = pb["meta"]["H"]
+    errs = {}
+    for diffuse in ("wall", "node"):
+        o = oracle.Oracle(dict(pb["params"], l_mode="wall_fit", r_mode="wall_fit", diffuse=diffuse),
+                          pb["solid"], pb["links"])
+        _, res = o.run_to_steady(1e-13, 100, max_steps=50_000)
+        assert res <= 1e-13
+        _, ux, _ = o.moments()
+        g = o.globals
+        uc = 1e-6 * h * h / (8 * g["nu"])
+        U = P.poiseuille_profile(pb["meta"]["y"], h, g["L1"], g["L2"], 0.1)
+        errs[diffuse] = np.max(np.abs(ux[1:-1, :] / uc - U[:, None])) / U.max()
+    assert errs["wall"] < 1e-9, errs
+    assert errs["node"] > 0.1, errs
+
+
+def test_wall_fit_inclined_channel():
+    """Inclined walls (non-uniform gamma) at Kn = 0.1, where every gamma is admissible: under the
+    literal reading the re-derived parameters follow the analytic profile more closely than the
+    node reading's parameters do under that reading, and about as closely as the node reading's
+    own scheme."""
+    tan_theta = 0.2
+    pb = G.inclined_channel(tan_theta, kn=0.1)
+    p = pb["params"]
+    ts = P.tau_s_of_kn(p["kn"], p["h"])
+    L1 = P.l1_poiseuille(1.0)
+    ana, uc = G.inclined_profile(pb, L1, P.l2_poiseuille(L1), (ts - 0.5) / 3)
+    fl = pb["solid"] == 0
+    c, s = 1 / math.sqrt(1 + tan_theta ** 2), tan_theta / math.sqrt(1 + tan_theta ** 2)
+    err = {}
+    for name, over in (("node", {}), ("wall_fit", WALL_FIT), ("wall_paper", dict(diffuse="wall"))):
+        o = oracle.Oracle(dict(p, **over), pb["solid"], pb["links"])
+        o.run_to_steady(1e-11, 100, 200_000)
+        _, ux, uy = o.moments()
+        err[name] = float(np.max(np.abs(ux * c + uy * s - ana)[fl]) / uc)
+    assert err["wall_fit"] < 0.8 * err["wall_paper"], err
+    assert err["wall_fit"] < 1.1 * err["node"], err
