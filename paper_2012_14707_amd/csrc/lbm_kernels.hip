@@ -125,6 +125,28 @@ struct Third<float> {
 template <typename T>
 __device__ __forceinline__ T split_mul(T x, T hi, T lo) { return fma(x, hi, x * lo); }
 
+// 1 / x: the correctly rounded quotient in fp64; in fp32 the hardware reciprocal (1 ulp) refined by
+// one Newton step, which replaces the ten-instruction IEEE division sequence.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// Loads and stores at a wave-uniform base plus a 32-bit per-lane byte offset, which the hardware
+// takes as a scalar base register plus one vector offset (no per-lane 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ base, uint32_t off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ base, uint32_t off, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + off) = v;
+}
+
 // The nine incoming populations g_i(x, t) (D2Q9 order of Eq. (Eq3)).
 template <typename T>
 struct Pop {
@@ -153,6 +175,38 @@ __device__ __forceinline__ Pop<T> pull(const T* __restrict__ pop, const T* __res
     return p;
 }
 #undef LBM_PULL
+
+// The same nine values for a wavefront whose 64 sites lie in one lattice row: the rows y, y - 1 and
+// y + 1 are wave-uniform, so each plane is read at a scalar row base plus the lane's byte offset of
+// x, x - 1 or x + 1; the few populations that come from a wall are then replaced from the link array.
+template <typename T>
+__device__ __forceinline__ Pop<T> pull_row(const T* __restrict__ pop, const T* __restrict__ lnk, uint64_t ps,
+                                           uint64_t row, uint64_t rowm, uint64_t rowp, uint32_t x, uint32_t xm,
+                                           uint32_t xp, uint32_t fl, uint32_t k0)
+{
+    const uint32_t ox = x * sizeof(T), om = xm * sizeof(T), op = xp * sizeof(T);
+    Pop<T> p;
+    p.g0 = ld_at(pop + row, ox);
+    p.g1 = ld_at(pop + 1 * ps + row, om);   // from (x-1, y)
+    p.g2 = ld_at(pop + 2 * ps + rowm, ox);  // from (x, y-1)
+    p.g3 = ld_at(pop + 3 * ps + row, op);   // from (x+1, y)
+    p.g4 = ld_at(pop + 4 * ps + rowp, ox);  // from (x, y+1)
+    p.g5 = ld_at(pop + 5 * ps + rowm, om);  // from (x-1, y-1)
+    p.g6 = ld_at(pop + 6 * ps + rowm, op);  // from (x+1, y-1)
+    p.g7 = ld_at(pop + 7 * ps + rowp, op);  // from (x+1, y+1)
+    p.g8 = ld_at(pop + 8 * ps + rowp, om);  // from (x-1, y+1)
+    if (fl) {
+        if (fl & 0x04u) p.g1 = lnk[k0 + rank_of(fl, 3)];
+        if (fl & 0x08u) p.g2 = lnk[k0 + rank_of(fl, 4)];
+        if (fl & 0x01u) p.g3 = lnk[k0];
+        if (fl & 0x02u) p.g4 = lnk[k0 + rank_of(fl, 2)];
+        if (fl & 0x40u) p.g5 = lnk[k0 + rank_of(fl, 7)];
+        if (fl & 0x80u) p.g6 = lnk[k0 + rank_of(fl, 8)];
+        if (fl & 0x10u) p.g7 = lnk[k0 + rank_of(fl, 5)];
+        if (fl & 0x20u) p.g8 = lnk[k0 + rank_of(fl, 6)];
+    }
+    return p;
+}
 
 // Density deviation and half-force velocity (Eq. (FluidMacr)) accumulated in fp64, for the
 // residual, the recorded velocity and the moments output.
@@ -191,7 +245,7 @@ __device__ __forceinline__ void collide(const Pop<T>& p, const StepArgs<T>& a, P
     const T rho = a.rho0 + dr;
     const T jx = (g1 - g3) + (g5 - g6) + (g8 - g7);
     const T jy = (g2 - g4) + (g5 + g6) - (g7 + g8);
-    const T irho = T(1) / rho;
+    const T irho = recip(rho);
     const T ux = (jx + T(0.5) * rho * a.ax) * irho;
     const T uy = (jy + T(0.5) * rho * a.ay) * irho;
     const T u2 = ux * ux + uy * uy;
@@ -410,14 +464,15 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
 // is that of step_tile (same collide / link_value / diffuse_term), so two fused steps give the
 // bits of two single steps.  Needs nx % 64 == 0 and ny % TY == 0.
 
-template <typename T>
-__device__ __forceinline__ void fused_site1(const StepArgs<T>& a, T* F, uint32_t s, uint32_t fl, uint32_t k0,
-                                            int rr, int cc, bool in_tile, int W, int P, bool node)
+// Step 1 of one site whose nine incoming populations p have been pulled: collision, the nine
+// post-collision values into LDS row rr, column cc, and (tile sites only) the operands of each of
+// its wall links into the staging area at j0 + rank, with the LDS slot of the solid neighbour
+// x + c_d that will receive the boundary value.
+template <typename T, bool NODE>
+__device__ __forceinline__ void fused_finish1(const StepArgs<T>& a, T* F, const LinkStage<T>& st, uint32_t* tg,
+                                              const Pop<T>& p, uint32_t fl, uint32_t j0, int rr, int cc,
+                                              bool in_tile, int W, int P)
 {
-    if (fl == kSolid) return;
-    const Geo& g = a.g;
-    const Nbr b = neighbours(s, g.nx, g.ny);
-    const Pop<T> p = pull(a.src.pop, a.src.link, g.ps, s, b, fl, k0);
     Post<T> o;
     collide(p, a, o);
     const int idx = rr * W + cc;
@@ -436,9 +491,13 @@ __device__ __forceinline__ void fused_site1(const StepArgs<T>& a, T* F, uint32_t
             const int cx = (d == 1 || d == 5 || d == 8) ? 1 : ((d == 3 || d == 6 || d == 7) ? -1 : 0);
             const int cy = (d == 2 || d == 5 || d == 6) ? 1 : ((d == 4 || d == 7 || d == 8) ? -1 : 0);
             const int i = (d <= 4) ? ((d + 1) & 3) + 1 : ((d - 3) & 3) + 5;
-            const T wd = node ? diffuse_term<T, true>(w, o.dr, o.rho, cu, o.u2)
-                              : diffuse_term<T, false>(w, o.dr, o.rho, cu, o.u2);
-            F[i * P + (rr + cy) * W + (cc + cx)] = link_value(a.coef, k0 + rank_of(fl, d), gb, hi, hb, o.rho, wd);
+            const uint32_t j = j0 + rank_of(fl, d);
+            st.gb[j] = gb;
+            st.hi[j] = hi;
+            st.hb[j] = hb;
+            st.rho[j] = o.rho;
+            st.dif[j] = diffuse_term<T, NODE>(w, o.dr, o.rho, cu, o.u2);
+            tg[j] = static_cast<uint32_t>(i * P + (rr + cy) * W + (cc + cx));
         });
     }
 }
@@ -455,42 +514,62 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles)
 template <typename T, bool WRITE_U, bool NODE, int TY>
 __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
 {
-    constexpr int W = kFuseTX + 2, R = TY + 2, P = R * W;
+    constexpr int W = kFuseTX + 2, R = TY + 2, P = R * W, NT = 64 * (TY + 3);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* F = reinterpret_cast<T*>(lds_raw);  // [9][R][W] post-collision values of step 1
-    T* stg = F + 9 * P;                    // [5][lds_links] link operands of step 2
+    T* stg = F + 9 * P;                    // [5][lds_links] link operands (step 1, then step 2)
     const LinkStage<T> st{stg, stg + a.lds_links, stg + 2 * a.lds_links, stg + 3 * a.lds_links,
                           stg + 4 * a.lds_links};
-    uint32_t* krow = reinterpret_cast<uint32_t*>(stg + 5 * a.lds_links);  // [TY] first link of each row
-    uint32_t* orow = krow + TY;                                            // [TY + 1] stage offsets
-    uint32_t* k0s = orow + TY + 1;                                         // [TY][64]
-    uint8_t* fls = reinterpret_cast<uint8_t*>(k0s + TY * kFuseTX);         // [TY][64]
+    uint32_t* tg = reinterpret_cast<uint32_t*>(stg + 5 * a.lds_links);   // [lds_links] F slot of each link
+    uint32_t* krow = tg + a.lds_links;                                    // [TY] first link of each row
+    uint32_t* orow = krow + TY;                                           // [TY + 1] stage offsets
+    uint32_t* k0s = orow + TY + 1;                                        // [TY][64]
+    uint8_t* fls = reinterpret_cast<uint8_t*>(k0s + TY * kFuseTX);        // [TY][64]
 
     const Geo& g = a.g;
     const uint32_t tiles_x = g.nx / kFuseTX;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t x0 = (tile % tiles_x) * kFuseTX, y0 = (tile / tiles_x) * TY;
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-
-    if (tid < TY) {
-        const uint32_t c = ((y0 + tid) * g.nx + x0) / kChunk;
-        const uint32_t kb = static_cast<uint32_t>(g.chunk_base[c]);
-        krow[tid] = kb;
-        orow[tid + 1] = static_cast<uint32_t>(g.chunk_base[c + 1]) - kb;
-    }
+    const int tid = threadIdx.x, lane = tid % 64;
+    const int wave = static_cast<int>(uniform(static_cast<uint32_t>(tid) / 64u));
+    const uint64_t ps = g.ps;
 
     if (wave < R) {
-        // step 1: wave w takes LDS row w (tile row w - 1; rows -1 and TY are the halo rows)
+        // step 1: wave w takes LDS row w (tile row w - 1; rows -1 and TY are the halo rows).  The
+        // wave's 64 sites are one chunk of one lattice row, so rows and the chunk are wave-uniform.
         const int rr = wave;
         const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
-        const uint32_t s = y * g.nx + x0 + lane;
-        const SiteLinks sl = site_links(g, s);
+        const uint32_t ym = (y == 0) ? g.ny - 1 : y - 1, yp = (y + 1 == g.ny) ? 0 : y + 1;
+        const uint64_t row = uint64_t(y) * g.nx;
+        const uint32_t x = x0 + lane;
+        const uint32_t fl = ld_at(g.flags + row, x);
+        const uint32_t nlink = (fl != kSolid) ? static_cast<uint32_t>(__popc(fl)) : 0u;
+        const uint32_t kb = static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk]);
+        const uint32_t k0 = kb + wave_prefix4(nlink);
         const bool in_tile = rr >= 1 && rr <= TY;
+        uint32_t j0 = 0;
         if (in_tile) {
-            k0s[(rr - 1) * kFuseTX + lane] = sl.k0;
-            fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(sl.fl);
+            // staging offset of this tile row: the links of the tile rows above it
+            uint32_t off = 0;
+            for (int q = 0; q < rr - 1; ++q) {
+                const uint32_t c = ((y0 + q) * g.nx + x0) / kChunk;
+                off += static_cast<uint32_t>(g.chunk_base[c + 1] - g.chunk_base[c]);
+            }
+            j0 = off + (k0 - kb);
+            k0s[(rr - 1) * kFuseTX + lane] = k0;
+            fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(fl);
+            if (lane == 0) {
+                krow[rr - 1] = kb;
+                orow[rr - 1] = off;
+                if (rr == TY) orow[TY] = off + static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk + 1]) - kb;
+            }
         }
-        fused_site1(a, F, s, sl.fl, sl.k0, rr, lane + 1, in_tile, W, P, NODE);
+        if (fl != kSolid) {
+            const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
+            const Pop<T> p = pull_row(a.src.pop, a.src.link, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x,
+                                      xm, xp, fl, k0);
+            fused_finish1<T, NODE>(a, F, st, tg, p, fl, j0, rr, lane + 1, in_tile, W, P);
+        }
     } else if (lane < 2 * R) {
         // the last wave: halo columns x0 - 1 (last site of its chunk) and x0 + 64 (first of its chunk)
         const int rr = lane >> 1, side = lane & 1;
@@ -498,26 +577,43 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
         const uint32_t x = side ? ((x0 + kFuseTX == g.nx) ? 0 : x0 + kFuseTX) : (x0 == 0 ? g.nx - 1 : x0 - 1);
         const uint32_t s = y * g.nx + x;
         const uint32_t fl = g.flags[s];
-        uint32_t k0 = 0;
-        if (fl != kSolid)
-            k0 = side ? static_cast<uint32_t>(g.chunk_base[s / kChunk])
-                      : static_cast<uint32_t>(g.chunk_base[s / kChunk + 1]) - static_cast<uint32_t>(__popc(fl));
-        fused_site1(a, F, s, fl, k0, rr, side ? W - 1 : 0, false, W, P, NODE);
+        if (fl != kSolid) {
+            const uint32_t k0 = side ? static_cast<uint32_t>(g.chunk_base[s / kChunk])
+                                     : static_cast<uint32_t>(g.chunk_base[s / kChunk + 1]) -
+                                           static_cast<uint32_t>(__popc(fl));
+            Nbr b;
+            b.x = x;
+            b.xm = (x == 0) ? g.nx - 1 : x - 1;
+            b.xp = (x + 1 == g.nx) ? 0 : x + 1;
+            b.row = y * g.nx;
+            b.rowm = ((y == 0) ? g.ny - 1 : y - 1) * g.nx;
+            b.rowp = ((y + 1 == g.ny) ? 0 : y + 1) * g.nx;
+            const Pop<T> p = pull(a.src.pop, a.src.link, ps, s, b, fl, k0);
+            fused_finish1<T, NODE>(a, F, st, tg, p, fl, 0, rr, side ? W - 1 : 0, false, W, P);
+        }
     }
     __syncthreads();
-    if (tid == 0) {
-        orow[0] = 0;
-        for (int r = 0; r < TY; ++r) orow[r + 1] += orow[r];
+
+    // the boundary values of step 1, link-parallel, into the LDS slots of the solid neighbours
+    const uint32_t total = orow[TY];
+    const LinkCoef<T> c = a.coef;
+    for (uint32_t jj = tid; jj < total; jj += NT) {
+        int r = 0;
+        while (jj >= orow[r + 1]) ++r;
+        const uint32_t k = krow[r] + (jj - orow[r]);
+        F[tg[jj]] = link_value(c, k, st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
     }
     __syncthreads();
 
     // step 2: wave r takes tile row r, pulling from LDS
     if (wave < TY) {
         const int r = wave;
-        const uint32_t s = (y0 + r) * g.nx + x0 + lane;
+        const uint64_t row = uint64_t(y0 + r) * g.nx;
+        const uint32_t s = static_cast<uint32_t>(row) + x0 + lane;
+        const uint32_t ox = (x0 + lane) * sizeof(T);
         const uint32_t fl = fls[r * kFuseTX + lane];
         const bool store_line = line_has(fl != kSolid, sizeof(T));
-        const uint64_t ps = g.ps;
+        T* __restrict__ dst = a.dst.pop + row;
         if (fl != kSolid) {
             const int idx = (r + 1) * W + lane + 1;
             Pop<T> p;
@@ -539,16 +635,15 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
             }
             Post<T> o;
             collide(p, a, o);
-            T* __restrict__ dst = a.dst.pop;
-            dst[s] = o.h0;
-            dst[1 * ps + s] = o.h1;
-            dst[2 * ps + s] = o.h2;
-            dst[3 * ps + s] = o.h3;
-            dst[4 * ps + s] = o.h4;
-            dst[5 * ps + s] = o.h5;
-            dst[6 * ps + s] = o.h6;
-            dst[7 * ps + s] = o.h7;
-            dst[8 * ps + s] = o.h8;
+            st_at(dst, ox, o.h0);
+            st_at(dst + 1 * ps, ox, o.h1);
+            st_at(dst + 2 * ps, ox, o.h2);
+            st_at(dst + 3 * ps, ox, o.h3);
+            st_at(dst + 4 * ps, ox, o.h4);
+            st_at(dst + 5 * ps, ox, o.h5);
+            st_at(dst + 6 * ps, ox, o.h6);
+            st_at(dst + 7 * ps, ox, o.h7);
+            st_at(dst + 8 * ps, ox, o.h8);
             if (fl) {
                 const uint32_t j0 = orow[r] + (k0s[r * kFuseTX + lane] - krow[r]);
                 for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
@@ -561,16 +656,13 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
                 });
             }
         } else if (store_line) {
-            T* __restrict__ dst = a.dst.pop;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dst[i * ps + s] = T(0);
+            for (int i = 0; i < 9; ++i) st_at(dst + i * ps, ox, T(0));
         }
     }
     __syncthreads();
-    // the tile's boundary values, link-parallel over its rows' contiguous link ranges (coalesced)
-    const uint32_t total = orow[TY];
-    const LinkCoef<T> c = a.coef;
-    for (uint32_t jj = tid; jj < total; jj += 64 * (TY + 3)) {
+    // the tile's boundary values of step 2, link-parallel over its rows' contiguous link ranges
+    for (uint32_t jj = tid; jj < total; jj += NT) {
         int r = 0;
         while (jj >= orow[r + 1]) ++r;
         const uint32_t k = krow[r] + (jj - orow[r]);
@@ -1038,8 +1130,8 @@ size_t step_lds_bytes(bool fp32, uint32_t max_links) { return 5 * (fp32 ? 4 : 8)
 size_t step2_lds_bytes(bool fp32, int rows, uint32_t max_links)
 {
     const size_t t = fp32 ? 4 : 8;
-    return t * (9 * size_t(rows + 2) * (kFuseTX + 2) + 5 * size_t(max_links)) + 4 * size_t(2 * rows + 1) +
-           5 * size_t(rows) * kFuseTX;
+    return t * (9 * size_t(rows + 2) * (kFuseTX + 2) + 5 * size_t(max_links)) + 4 * size_t(max_links) +
+           4 * size_t(2 * rows + 1) + 5 * size_t(rows) * kFuseTX;
 }
 
 namespace {
