@@ -22,6 +22,9 @@ FLAGS = [
     "-Wall",
     # packed fp32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so kernels that share a device
+    # function (the single-step and two-step kernels) round identically whatever the surrounding code
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,
 ]

@@ -251,14 +251,12 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
         release(c);
         return fail(LBM_E_GEOMETRY, "%u wall links in one 64-site chunk exceed the LDS staging area", c->lds_links);
     }
-    // two time steps per launch where the lattice tiles into 64 x rows blocks
-    // Two time steps per launch by default where it is faster: fp64 storage, whose single step is
-    // bound by HBM traffic.  The fp32 single step already keeps the vector ALUs about 65% busy and
-    // the two-step kernel issues as many instructions per site update, so it does not gain there.
+    // two time steps per launch by default where the lattice tiles into 64 x rows blocks (half the
+    // HBM traffic per step; faster in both precisions)
     for (int rows : {8, 4}) {
         uint32_t links = 0;
         if (c->fusion_fits(rows, &links)) {
-            c->fuse = c->fp32() ? 1 : 2;
+            c->fuse = 2;
             c->fuse_rows = rows;
             c->fuse_links = links;
             break;

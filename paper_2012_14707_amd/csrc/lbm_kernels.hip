@@ -321,9 +321,23 @@ __device__ __forceinline__ void collide(const Pop<T>& p, const StepArgs<T>& a, P
 // Boundary value of Eq. (EqNewBDSC) in deviation form for link k:
 //   g_i(x, t+1) = a1 g_ibar + a2 g'_i + a3 g'_ibar + beta rho + kappa w_i (drho + rho phi_i(u)).
 template <typename T>
+struct LinkCoefs {
+    T a1, a2, a3, beta, kappa;
+};
+template <typename T>
+__device__ __forceinline__ LinkCoefs<T> link_coefs(const LinkCoef<T>& c, uint32_t k)
+{
+    return LinkCoefs<T>{c.a1[k], c.a2[k], c.a3[k], c.beta[k], c.kappa[k]};
+}
+template <typename T>
+__device__ __forceinline__ T link_value(const LinkCoefs<T>& w, T gb, T hi, T hb, T rho, T wdif)
+{
+    return w.a1 * gb + w.a2 * hi + w.a3 * hb + w.beta * rho + w.kappa * wdif;
+}
+template <typename T>
 __device__ __forceinline__ T link_value(const LinkCoef<T>& c, uint32_t k, T gb, T hi, T hb, T rho, T wdif)
 {
-    return c.a1[k] * gb + c.a2[k] * hi + c.a3[k] * hb + c.beta[k] * rho + c.kappa[k] * wdif;
+    return link_value(link_coefs(c, k), gb, hi, hb, rho, wdif);
 }
 
 // w_i (drho + rho phi_i(u)) (node reading) or w_i drho (wall reading, where the wall equilibrium
@@ -511,20 +525,27 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles)
     return (b % 8u) * (ntiles / 8u) + b / 8u;
 }
 
-template <typename T, bool WRITE_U, bool NODE, int TY>
-__global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
+// Block of the two-step kernel: (TY + 2) / RPW step-1 waves, each taking RPW LDS rows, and one wave
+// for the two halo columns.
+template <int TY, int RPW>
+constexpr int step2_threads()
 {
-    constexpr int W = kFuseTX + 2, R = TY + 2, P = R * W, NT = 64 * (TY + 3);
+    return 64 * ((TY + 2) / RPW + 1);
+}
+template <typename T, bool WRITE_U, bool NODE, int TY, int RPW>
+__global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const StepArgs<T> a)
+{
+    static_assert((TY + 2) % RPW == 0 && TY % RPW == 0, "rows per wave must divide the tile rows");
+    constexpr int W = kFuseTX + 2, R = TY + 2, P = R * W, NT = step2_threads<TY, RPW>();
+    constexpr int NW1 = R / RPW;  // step-1 row waves; wave NW1 takes the halo columns
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* F = reinterpret_cast<T*>(lds_raw);  // [9][R][W] post-collision values of step 1
     T* stg = F + 9 * P;                    // [5][lds_links] link operands (step 1, then step 2)
     const LinkStage<T> st{stg, stg + a.lds_links, stg + 2 * a.lds_links, stg + 3 * a.lds_links,
                           stg + 4 * a.lds_links};
     uint32_t* tg = reinterpret_cast<uint32_t*>(stg + 5 * a.lds_links);   // [lds_links] F slot of each link
-    uint32_t* krow = tg + a.lds_links;                                    // [TY] first link of each row
-    uint32_t* orow = krow + TY;                                           // [TY + 1] stage offsets
-    uint32_t* k0s = orow + TY + 1;                                        // [TY][64]
-    uint8_t* fls = reinterpret_cast<uint8_t*>(k0s + TY * kFuseTX);        // [TY][64]
+    uint32_t* j0s = tg + a.lds_links;                                     // [TY][64] first staging slot
+    uint8_t* fls = reinterpret_cast<uint8_t*>(j0s + TY * kFuseTX);        // [TY][64] flag bytes
 
     const Geo& g = a.g;
     const uint32_t tiles_x = g.nx / kFuseTX;
@@ -534,41 +555,78 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
     const int wave = static_cast<int>(uniform(static_cast<uint32_t>(tid) / 64u));
     const uint64_t ps = g.ps;
 
-    if (wave < R) {
-        // step 1: wave w takes LDS row w (tile row w - 1; rows -1 and TY are the halo rows).  The
-        // wave's 64 sites are one chunk of one lattice row, so rows and the chunk are wave-uniform.
-        const int rr = wave;
-        const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
-        const uint32_t ym = (y == 0) ? g.ny - 1 : y - 1, yp = (y + 1 == g.ny) ? 0 : y + 1;
-        const uint64_t row = uint64_t(y) * g.nx;
-        const uint32_t x = x0 + lane;
-        const uint32_t fl = ld_at(g.flags + row, x);
-        const uint32_t nlink = (fl != kSolid) ? static_cast<uint32_t>(__popc(fl)) : 0u;
-        const uint32_t kb = static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk]);
-        const uint32_t k0 = kb + wave_prefix4(nlink);
-        const bool in_tile = rr >= 1 && rr <= TY;
-        uint32_t j0 = 0;
-        if (in_tile) {
-            // staging offset of this tile row: the links of the tile rows above it
-            uint32_t off = 0;
-            for (int q = 0; q < rr - 1; ++q) {
-                const uint32_t c = ((y0 + q) * g.nx + x0) / kChunk;
-                off += static_cast<uint32_t>(g.chunk_base[c + 1] - g.chunk_base[c]);
+    // Link ranges of the tile rows (wave-uniform): row q owns links [kq[q], kq[q] + oq[q+1] - oq[q]),
+    // staged from slot oq[q].
+    uint32_t kq[TY], oq[TY + 1];
+    oq[0] = 0;
+#pragma unroll
+    for (int q = 0; q < TY; ++q) {
+        const uint32_t c = ((y0 + q) * g.nx + x0) / kChunk;
+        kq[q] = static_cast<uint32_t>(g.chunk_base[c]);
+        oq[q + 1] = oq[q] + (static_cast<uint32_t>(g.chunk_base[c + 1]) - kq[q]);
+    }
+    const uint32_t total = oq[TY];
+    // link index of staging slot j
+    auto link_of = [&](uint32_t j) __attribute__((always_inline)) {
+        uint32_t k = j + kq[0];
+#pragma unroll
+        for (int q = 1; q < TY; ++q)
+            if (j >= oq[q]) k = j - oq[q] + kq[q];
+        return k;
+    };
+    // fp32: the coefficients of this thread's first staging slot are fetched now and used by both
+    // steps (in fp64 the ten extra live registers would cost a resident block)
+    const LinkCoef<T> c = a.coef;
+    const bool has1 = sizeof(T) == 4 && static_cast<uint32_t>(tid) < total;
+    const uint32_t k1 = link_of(static_cast<uint32_t>(tid));
+    LinkCoefs<T> w1{};
+    if (has1) w1 = link_coefs(c, k1);
+
+    if (wave < NW1) {
+        // step 1: wave w takes LDS rows w RPW .. w RPW + RPW - 1 (LDS row rr is tile row rr - 1;
+        // rows -1 and TY are the halo rows).  Each row of a wave is one chunk of one lattice row,
+        // so rows and chunks are wave-uniform.  With several rows per wave all are pulled before
+        // any is collided; with one, pull and collision stay together (fewer live registers).
+        uint32_t fl[RPW], k0[RPW], j0[RPW];
+        Pop<T> p[RPW];
+#pragma unroll
+        for (int h = 0; h < RPW; ++h) {
+            const int rr = wave * RPW + h;
+            const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
+            const uint32_t ym = (y == 0) ? g.ny - 1 : y - 1, yp = (y + 1 == g.ny) ? 0 : y + 1;
+            const uint64_t row = uint64_t(y) * g.nx;
+            const uint32_t x = x0 + lane;
+            fl[h] = ld_at(g.flags + row, x);
+            const uint32_t nlink = (fl[h] != kSolid) ? static_cast<uint32_t>(__popc(fl[h])) : 0u;
+            const uint32_t kb = static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk]);
+            k0[h] = kb + wave_prefix4(nlink);
+            j0[h] = 0;
+            if (rr >= 1 && rr <= TY) {
+                uint32_t off = 0;  // staging offset of this tile row: the links of the tile rows above
+                for (int q = 0; q < rr - 1; ++q) {
+                    const uint32_t cq = ((y0 + q) * g.nx + x0) / kChunk;
+                    off += static_cast<uint32_t>(g.chunk_base[cq + 1] - g.chunk_base[cq]);
+                }
+                j0[h] = off + (k0[h] - kb);
+                j0s[(rr - 1) * kFuseTX + lane] = j0[h];
+                fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(fl[h]);
             }
-            j0 = off + (k0 - kb);
-            k0s[(rr - 1) * kFuseTX + lane] = k0;
-            fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(fl);
-            if (lane == 0) {
-                krow[rr - 1] = kb;
-                orow[rr - 1] = off;
-                if (rr == TY) orow[TY] = off + static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk + 1]) - kb;
+            if (fl[h] != kSolid) {
+                const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
+                p[h] = pull_row(a.src.pop, a.src.link, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x, xm, xp,
+                                fl[h], k0[h]);
+                if constexpr (RPW == 1)
+                    fused_finish1<T, NODE>(a, F, st, tg, p[h], fl[h], j0[h], rr, lane + 1, rr >= 1 && rr <= TY, W, P);
             }
         }
-        if (fl != kSolid) {
-            const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
-            const Pop<T> p = pull_row(a.src.pop, a.src.link, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x,
-                                      xm, xp, fl, k0);
-            fused_finish1<T, NODE>(a, F, st, tg, p, fl, j0, rr, lane + 1, in_tile, W, P);
+        if constexpr (RPW > 1) {
+#pragma unroll
+            for (int h = 0; h < RPW; ++h) {
+                const int rr = wave * RPW + h;
+                if (fl[h] != kSolid)
+                    fused_finish1<T, NODE>(a, F, st, tg, p[h], fl[h], j0[h], rr, lane + 1, rr >= 1 && rr <= TY, W,
+                                           P);
+            }
         }
     } else if (lane < 2 * R) {
         // the last wave: halo columns x0 - 1 (last site of its chunk) and x0 + 64 (first of its chunk)
@@ -595,37 +653,32 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
     __syncthreads();
 
     // the boundary values of step 1, link-parallel, into the LDS slots of the solid neighbours
-    const uint32_t total = orow[TY];
-    const LinkCoef<T> c = a.coef;
-    for (uint32_t jj = tid; jj < total; jj += NT) {
-        int r = 0;
-        while (jj >= orow[r + 1]) ++r;
-        const uint32_t k = krow[r] + (jj - orow[r]);
-        F[tg[jj]] = link_value(c, k, st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
-    }
+    if (has1) F[tg[tid]] = link_value(w1, st.gb[tid], st.hi[tid], st.hb[tid], st.rho[tid], st.dif[tid]);
+    for (uint32_t jj = has1 ? tid + NT : tid; jj < total; jj += NT)
+        F[tg[jj]] = link_value(c, link_of(jj), st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
     __syncthreads();
 
-    // step 2: wave r takes tile row r, pulling from LDS
-    if (wave < TY) {
-        const int r = wave;
+    // step 2: wave w takes tile rows w RPW .. w RPW + RPW - 1, pulling from LDS (with several rows
+    // per wave, all rows' LDS loads are issued first)
+    auto load2 = [&](int r, Pop<T>& p) __attribute__((always_inline)) {
+        const int idx = (r + 1) * W + lane + 1;
+        p.g0 = F[idx];
+        p.g1 = F[1 * P + idx - 1];      // from (x-1, y)
+        p.g2 = F[2 * P + idx - W];      // from (x, y-1)
+        p.g3 = F[3 * P + idx + 1];      // from (x+1, y)
+        p.g4 = F[4 * P + idx + W];      // from (x, y+1)
+        p.g5 = F[5 * P + idx - W - 1];  // from (x-1, y-1)
+        p.g6 = F[6 * P + idx - W + 1];  // from (x+1, y-1)
+        p.g7 = F[7 * P + idx + W + 1];  // from (x+1, y+1)
+        p.g8 = F[8 * P + idx + W - 1];  // from (x-1, y+1)
+    };
+    auto finish2 = [&](int r, uint32_t fl, const Pop<T>& p) __attribute__((always_inline)) {
         const uint64_t row = uint64_t(y0 + r) * g.nx;
         const uint32_t s = static_cast<uint32_t>(row) + x0 + lane;
         const uint32_t ox = (x0 + lane) * sizeof(T);
-        const uint32_t fl = fls[r * kFuseTX + lane];
         const bool store_line = line_has(fl != kSolid, sizeof(T));
         T* __restrict__ dst = a.dst.pop + row;
         if (fl != kSolid) {
-            const int idx = (r + 1) * W + lane + 1;
-            Pop<T> p;
-            p.g0 = F[idx];
-            p.g1 = F[1 * P + idx - 1];      // from (x-1, y)
-            p.g2 = F[2 * P + idx - W];      // from (x, y-1)
-            p.g3 = F[3 * P + idx + 1];      // from (x+1, y)
-            p.g4 = F[4 * P + idx + W];      // from (x, y+1)
-            p.g5 = F[5 * P + idx - W - 1];  // from (x-1, y-1)
-            p.g6 = F[6 * P + idx - W + 1];  // from (x+1, y-1)
-            p.g7 = F[7 * P + idx + W + 1];  // from (x+1, y+1)
-            p.g8 = F[8 * P + idx + W - 1];  // from (x-1, y+1)
             if (WRITE_U) {
                 double dr_d, rho_d, ux_d, uy_d;
                 macro_fp64(p, static_cast<double>(a.rho0), static_cast<double>(a.ax), static_cast<double>(a.ay),
@@ -645,7 +698,7 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
             st_at(dst + 7 * ps, ox, o.h7);
             st_at(dst + 8 * ps, ox, o.h8);
             if (fl) {
-                const uint32_t j0 = orow[r] + (k0s[r * kFuseTX + lane] - krow[r]);
+                const uint32_t j0 = j0s[r * kFuseTX + lane];
                 for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
                     const uint32_t j = j0 + rank_of(fl, d);
                     st.gb[j] = gb;
@@ -659,13 +712,30 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_step2(const StepArgs<T> a)
 #pragma unroll
             for (int i = 0; i < 9; ++i) st_at(dst + i * ps, ox, T(0));
         }
+    };
+    if (wave < TY / RPW) {
+        if constexpr (RPW == 1) {
+            const uint32_t fl = fls[wave * kFuseTX + lane];
+            Pop<T> p;
+            if (fl != kSolid) load2(wave, p);
+            finish2(wave, fl, p);
+        } else {
+            uint32_t fl[RPW];
+            Pop<T> p[RPW];
+#pragma unroll
+            for (int h = 0; h < RPW; ++h) {
+                fl[h] = fls[(wave * RPW + h) * kFuseTX + lane];
+                if (fl[h] != kSolid) load2(wave * RPW + h, p[h]);
+            }
+#pragma unroll
+            for (int h = 0; h < RPW; ++h) finish2(wave * RPW + h, fl[h], p[h]);
+        }
     }
     __syncthreads();
     // the tile's boundary values of step 2, link-parallel over its rows' contiguous link ranges
-    for (uint32_t jj = tid; jj < total; jj += NT) {
-        int r = 0;
-        while (jj >= orow[r + 1]) ++r;
-        const uint32_t k = krow[r] + (jj - orow[r]);
+    if (has1) a.dst.link[k1] = link_value(w1, st.gb[tid], st.hi[tid], st.hb[tid], st.rho[tid], st.dif[tid]);
+    for (uint32_t jj = has1 ? tid + NT : tid; jj < total; jj += NT) {
+        const uint32_t k = link_of(jj);
         a.dst.link[k] = link_value(c, k, st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
     }
 }
@@ -1131,43 +1201,45 @@ size_t step2_lds_bytes(bool fp32, int rows, uint32_t max_links)
 {
     const size_t t = fp32 ? 4 : 8;
     return t * (9 * size_t(rows + 2) * (kFuseTX + 2) + 5 * size_t(max_links)) + 4 * size_t(max_links) +
-           4 * size_t(2 * rows + 1) + 5 * size_t(rows) * kFuseTX;
+           5 * size_t(rows) * kFuseTX;
 }
 
 namespace {
 
-template <typename T, int TY>
+template <typename T, int TY, int RPW>
 hipError_t launch_step2_rows(const StepArgs<T>& a, bool write_u, bool node, hipStream_t stream)
 {
     const uint32_t grid = (a.g.nx / kFuseTX) * (a.g.ny / TY);
     const size_t lds = step2_lds_bytes(sizeof(T) == 4, TY, a.lds_links);
-    const dim3 block(64 * (TY + 3));
+    const dim3 block(step2_threads<TY, RPW>());
     if (write_u) {
         if (node)
-            hipLaunchKernelGGL((k_step2<T, true, true, TY>), dim3(grid), block, lds, stream, a);
+            hipLaunchKernelGGL((k_step2<T, true, true, TY, RPW>), dim3(grid), block, lds, stream, a);
         else
-            hipLaunchKernelGGL((k_step2<T, true, false, TY>), dim3(grid), block, lds, stream, a);
+            hipLaunchKernelGGL((k_step2<T, true, false, TY, RPW>), dim3(grid), block, lds, stream, a);
     } else {
         if (node)
-            hipLaunchKernelGGL((k_step2<T, false, true, TY>), dim3(grid), block, lds, stream, a);
+            hipLaunchKernelGGL((k_step2<T, false, true, TY, RPW>), dim3(grid), block, lds, stream, a);
         else
-            hipLaunchKernelGGL((k_step2<T, false, false, TY>), dim3(grid), block, lds, stream, a);
+            hipLaunchKernelGGL((k_step2<T, false, false, TY, RPW>), dim3(grid), block, lds, stream, a);
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
+// fp64: one LDS row per step-1 wave (the LDS tile already limits a CU to two blocks); fp32: two rows
+// per wave, so that five smaller blocks share a CU and each lane has two sites' loads in flight.
 hipError_t launch_step2_f64(const StepArgs<double>& a, int rows, bool write_u, bool node, hipStream_t stream)
 {
-    return rows == 4 ? launch_step2_rows<double, 4>(a, write_u, node, stream)
-                     : launch_step2_rows<double, 8>(a, write_u, node, stream);
+    return rows == 4 ? launch_step2_rows<double, 4, 1>(a, write_u, node, stream)
+                     : launch_step2_rows<double, 8, 1>(a, write_u, node, stream);
 }
 
 hipError_t launch_step2_f32(const StepArgs<float>& a, int rows, bool write_u, bool node, hipStream_t stream)
 {
-    return rows == 4 ? launch_step2_rows<float, 4>(a, write_u, node, stream)
-                     : launch_step2_rows<float, 8>(a, write_u, node, stream);
+    return rows == 4 ? launch_step2_rows<float, 4, 2>(a, write_u, node, stream)
+                     : launch_step2_rows<float, 8, 2>(a, write_u, node, stream);
 }
 
 hipError_t launch_step_f64(const StepArgs<double>& a, int block, bool write_u, bool node, hipStream_t stream)

@@ -58,8 +58,8 @@ def test_two_step_launch_bitwise(case, precision):
     pb = _problem(case)
     fused = lbm.Lattice(pb, precision=precision)
     single = lbm.Lattice(pb, precision=precision)
-    # default: two steps per launch for fp64 storage where the lattice tiles, one for fp32
-    assert fused.info["steps_per_launch"] == (2 if precision == "fp64" else 1)
+    # default: two steps per launch where the lattice tiles
+    assert fused.info["steps_per_launch"] == 2
     fused.set_fusion(2)
     assert fused.info["steps_per_launch"] == 2
     single.set_fusion(1)
