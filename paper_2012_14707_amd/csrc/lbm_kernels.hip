@@ -66,7 +66,23 @@ __device__ __forceinline__ bool line_has(bool any, int bytes)
 // Rank of link direction d (1..8) among the links of a site with flag byte fl.
 __device__ __forceinline__ uint32_t rank_of(uint32_t fl, int d)
 {
-    return static_cast<uint32_t>(__popc(fl & ((1u << (d - 1)) - 1u)));
+    return d == 1 ? 0u : static_cast<uint32_t>(__popc(__builtin_amdgcn_ubfe(fl, 0u, static_cast<uint32_t>(d - 1))));
+}
+
+// The flag byte as an opaque 32-bit value.  The compiler knows a byte load is below 256 and then
+// tests single bits through sub-dword selects that cost an extra move each; hiding the range lets
+// every test take one AND with an inline constant.  Applied only where the flags are tested after
+// the loads that do not depend on them have been issued (the value must be present here).
+__device__ __forceinline__ uint32_t opaque_flags(uint32_t fl)
+{
+    asm("" : "+v"(fl));
+    return fl;
+}
+
+// Bit d - 1 of the flag byte: site has a wall link in direction d.
+__device__ __forceinline__ bool has_link(uint32_t fl, int d)
+{
+    return __builtin_amdgcn_ubfe(fl, static_cast<uint32_t>(d - 1), 1u) != 0u;
 }
 
 struct Nbr {
@@ -178,11 +194,11 @@ __device__ __forceinline__ Pop<T> pull(const T* __restrict__ pop, const T* __res
 
 // The same nine values for a wavefront whose 64 sites lie in one lattice row: the rows y, y - 1 and
 // y + 1 are wave-uniform, so each plane is read at a scalar row base plus the lane's byte offset of
-// x, x - 1 or x + 1; the few populations that come from a wall are then replaced from the link array.
+// x, x - 1 or x + 1.  The loads do not depend on the site's flags (solid sites read slots they then
+// ignore), so they are in flight together with the flag load.
 template <typename T>
-__device__ __forceinline__ Pop<T> pull_row(const T* __restrict__ pop, const T* __restrict__ lnk, uint64_t ps,
-                                           uint64_t row, uint64_t rowm, uint64_t rowp, uint32_t x, uint32_t xm,
-                                           uint32_t xp, uint32_t fl, uint32_t k0)
+__device__ __forceinline__ Pop<T> pull_planes(const T* __restrict__ pop, uint64_t ps, uint64_t row, uint64_t rowm,
+                                              uint64_t rowp, uint32_t x, uint32_t xm, uint32_t xp)
 {
     const uint32_t ox = x * sizeof(T), om = xm * sizeof(T), op = xp * sizeof(T);
     Pop<T> p;
@@ -195,17 +211,24 @@ __device__ __forceinline__ Pop<T> pull_row(const T* __restrict__ pop, const T* _
     p.g6 = ld_at(pop + 6 * ps + rowm, op);  // from (x+1, y-1)
     p.g7 = ld_at(pop + 7 * ps + rowp, op);  // from (x+1, y+1)
     p.g8 = ld_at(pop + 8 * ps + rowp, om);  // from (x-1, y+1)
-    if (fl) {
-        if (fl & 0x04u) p.g1 = lnk[k0 + rank_of(fl, 3)];
-        if (fl & 0x08u) p.g2 = lnk[k0 + rank_of(fl, 4)];
-        if (fl & 0x01u) p.g3 = lnk[k0];
-        if (fl & 0x02u) p.g4 = lnk[k0 + rank_of(fl, 2)];
-        if (fl & 0x40u) p.g5 = lnk[k0 + rank_of(fl, 7)];
-        if (fl & 0x80u) p.g6 = lnk[k0 + rank_of(fl, 8)];
-        if (fl & 0x10u) p.g7 = lnk[k0 + rank_of(fl, 5)];
-        if (fl & 0x20u) p.g8 = lnk[k0 + rank_of(fl, 6)];
-    }
     return p;
+}
+
+// Replaces the populations that come from a wall by the link array entries of a fluid site with flag
+// byte fl (nonzero, not solid) whose first link is k0.
+template <typename T>
+__device__ __forceinline__ void pull_links(Pop<T>& p, const T* __restrict__ lnk, uint32_t fl, uint32_t k0)
+{
+    const uint32_t f = opaque_flags(fl);
+    const T* __restrict__ lk = lnk + k0;
+    if (has_link(f, 3)) p.g1 = lk[rank_of(f, 3)];
+    if (has_link(f, 4)) p.g2 = lk[rank_of(f, 4)];
+    if (has_link(f, 1)) p.g3 = lk[0];
+    if (has_link(f, 2)) p.g4 = lk[rank_of(f, 2)];
+    if (has_link(f, 7)) p.g5 = lk[rank_of(f, 7)];
+    if (has_link(f, 8)) p.g6 = lk[rank_of(f, 8)];
+    if (has_link(f, 5)) p.g7 = lk[rank_of(f, 5)];
+    if (has_link(f, 6)) p.g8 = lk[rank_of(f, 6)];
 }
 
 // Density deviation and half-force velocity (Eq. (FluidMacr)) accumulated in fp64, for the
@@ -342,39 +365,61 @@ __device__ __forceinline__ T link_value(const LinkCoef<T>& c, uint32_t k, T gb, 
 
 // w_i (drho + rho phi_i(u)) (node reading) or w_i drho (wall reading, where the wall equilibrium
 // is folded into beta), phi_i(u) = 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u^2 with cu = c_i.u.
+// With the site parts b = drho - 1.5 rho u^2 (node reading; b = drho in the wall reading), 3 rho and
+// 4.5 rho formed once per site, the term of link direction i is w_i (b + c_i.u (3 rho + 4.5 rho c_i.u)).
+template <typename T>
+struct DiffuseSite {
+    T b, r3, r45;
+};
 template <typename T, bool NODE>
-__device__ __forceinline__ T diffuse_term(T w, T dr, T rho, T cu, T u2)
+__device__ __forceinline__ DiffuseSite<T> diffuse_base(T dr, T rho, T u2)
 {
-    T dif = dr;
-    if (NODE) dif += rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * u2);
-    return w * dif;
+    return DiffuseSite<T>{NODE ? dr - T(1.5) * rho * u2 : dr, T(3) * rho, T(4.5) * rho};
+}
+template <typename T, bool NODE>
+__device__ __forceinline__ T diffuse_term(T w, const DiffuseSite<T>& ds, T cu)
+{
+    return NODE ? w * (cu * (ds.r45 * cu + ds.r3) + ds.b) : w * ds.b;
 }
 
-// Calls fn(d, g_ibar, g'_i, g'_ibar, w_i, c_i.u) for every wall link direction d of a site with flag
-// byte fl (the unknown population is i = opposite(d)).
+// Calls fn(d, rank, g_ibar, g'_i, g'_ibar, w_i, c_i.u) for every wall link direction d of a site
+// with flag byte fl (the unknown population is i = opposite(d); rank = the link's position among
+// the site's links).
 template <typename T, typename F>
 __device__ __forceinline__ void for_links(uint32_t fl, const Pop<T>& p, const Post<T>& o, F&& fn)
 {
     const T w1 = T(1.0 / 9.0), w5 = T(1.0 / 36.0);
-    if (fl & 0x01u) fn(1, p.g1, o.h3, o.h1, w1, -o.ux);          // toward E, unknown W
-    if (fl & 0x02u) fn(2, p.g2, o.h4, o.h2, w1, -o.uy);          // toward N, unknown S
-    if (fl & 0x04u) fn(3, p.g3, o.h1, o.h3, w1, o.ux);           // toward W, unknown E
-    if (fl & 0x08u) fn(4, p.g4, o.h2, o.h4, w1, o.uy);           // toward S, unknown N
-    if (fl & 0x10u) fn(5, p.g5, o.h7, o.h5, w5, -o.ux - o.uy);   // toward NE, unknown SW
-    if (fl & 0x20u) fn(6, p.g6, o.h8, o.h6, w5, o.ux - o.uy);    // toward NW, unknown SE
-    if (fl & 0x40u) fn(7, p.g7, o.h5, o.h7, w5, o.ux + o.uy);    // toward SW, unknown NE
-    if (fl & 0x80u) fn(8, p.g8, o.h6, o.h8, w5, -o.ux + o.uy);   // toward SE, unknown NW
+    if (has_link(fl, 1)) fn(1, 0u, p.g1, o.h3, o.h1, w1, -o.ux);                  // toward E, unknown W
+    if (has_link(fl, 2)) fn(2, rank_of(fl, 2), p.g2, o.h4, o.h2, w1, -o.uy);      // toward N, unknown S
+    if (has_link(fl, 3)) fn(3, rank_of(fl, 3), p.g3, o.h1, o.h3, w1, o.ux);       // toward W, unknown E
+    if (has_link(fl, 4)) fn(4, rank_of(fl, 4), p.g4, o.h2, o.h4, w1, o.uy);       // toward S, unknown N
+    if (has_link(fl, 5)) fn(5, rank_of(fl, 5), p.g5, o.h7, o.h5, w5, -o.ux - o.uy);  // toward NE, unknown SW
+    if (has_link(fl, 6)) fn(6, rank_of(fl, 6), p.g6, o.h8, o.h6, w5, o.ux - o.uy);   // toward NW, unknown SE
+    if (has_link(fl, 7)) fn(7, rank_of(fl, 7), p.g7, o.h5, o.h7, w5, o.ux + o.uy);   // toward SW, unknown NE
+    if (has_link(fl, 8)) fn(8, rank_of(fl, 8), p.g8, o.h6, o.h8, w5, -o.ux + o.uy);  // toward SE, unknown NW
 }
 
-// LDS staging of one link's operands: five arrays of lds_links entries.
+// LDS staging of one link's operands, one record per link (the five stores of a link share one
+// address).
 template <typename T>
-struct LinkStage {
-    T* gb;   // g_ibar(x, t), pre-collision, toward the wall
-    T* hi;   // g'_i(x, t), post-collision, away from the wall
-    T* hb;   // g'_ibar(x, t)
-    T* rho;  // rho(x, t)
-    T* dif;  // w_i (drho + rho phi_i(u)) in the node reading, w_i drho in the wall reading
+struct LinkRec {
+    T gb;   // g_ibar(x, t), pre-collision, toward the wall
+    T hi;   // g'_i(x, t), post-collision, away from the wall
+    T hb;   // g'_ibar(x, t)
+    T rho;  // rho(x, t)
+    T dif;  // w_i (drho + rho phi_i(u)) in the node reading, w_i drho in the wall reading
 };
+
+template <typename T>
+__device__ __forceinline__ T link_value(const LinkCoef<T>& c, uint32_t k, const LinkRec<T>& r)
+{
+    return link_value(c, k, r.gb, r.hi, r.hb, r.rho, r.dif);
+}
+template <typename T>
+__device__ __forceinline__ T link_value(const LinkCoefs<T>& w, const LinkRec<T>& r)
+{
+    return link_value(w, r.gb, r.hi, r.hb, r.rho, r.dif);
+}
 
 // One tile of BLOCK consecutive sites starting at `start` (a multiple of BLOCK) of the lattice
 // described by a.g: collision and streaming of its fluid sites, then the boundary values of its
@@ -395,9 +440,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
     const uint64_t ps = g.ps;
     const bool store_line = line_has(fl != kSolid, sizeof(T));
 
-    T* lds = reinterpret_cast<T*>(lds_raw);
-    const LinkStage<T> st{lds, lds + a.lds_links, lds + 2 * a.lds_links, lds + 3 * a.lds_links,
-                          lds + 4 * a.lds_links};
+    LinkRec<T>* st = reinterpret_cast<LinkRec<T>*>(lds_raw);
 
     if (fl != kSolid) {
         const Nbr b = neighbours(s, g.nx, g.ny);
@@ -430,17 +473,16 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
 
         if (fl) {
             // operands of Eq. (EqNewBDSC) for each wall link (x, d); the unknown is i = opposite(d)
-            const uint32_t j0 = k0 - kblk;
-            for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
-                const uint32_t j = j0 + rank_of(fl, d);
-                st.gb[j] = gb;
-                st.hi[j] = hi;
-                st.hb[j] = hb;
-                st.rho[j] = rho;
-                st.dif[j] = diffuse_term<T, NODE>(w, dr, rho, cu, u2);
+            LinkRec<T>* sp = st + (k0 - kblk);
+            const DiffuseSite<T> b = diffuse_base<T, NODE>(dr, rho, u2);
+            for_links(fl, p, o, [&](int, uint32_t rank, T gb, T hi, T hb, T w, T cu) {
+                sp[rank] = LinkRec<T>{gb, hi, hb, rho, diffuse_term<T, NODE>(w, b, cu)};
             });
         }
-    } else if (store_line && s < g.n) {
+    }
+    // solid sites that share a line with a fluid site: zeros in never-read slots keep the stores
+    // whole lines (a separate branch after the fluid one, so that a mixed wave issues its loads first)
+    if (fl == kSolid && store_line && s < g.n) {
         T* __restrict__ dst = a.dst.pop;
 #pragma unroll
         for (int i = 0; i < 9; ++i) dst[i * ps + s] = T(0);
@@ -453,7 +495,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, uint32_t start, 
         const LinkCoef<T> c = a.coef;
         for (uint32_t j = threadIdx.x; j < nl_blk; j += BLOCK) {
             const uint32_t k = kblk + j;
-            a.dst.link[k] = link_value(c, k, st.gb[j], st.hi[j], st.hb[j], st.rho[j], st.dif[j]);
+            a.dst.link[k] = link_value(c, k, st[j]);
         }
     }
 }
@@ -483,7 +525,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
 // its wall links into the staging area at j0 + rank, with the LDS slot of the solid neighbour
 // x + c_d that will receive the boundary value.
 template <typename T, bool NODE>
-__device__ __forceinline__ void fused_finish1(const StepArgs<T>& a, T* F, const LinkStage<T>& st, uint32_t* tg,
+__device__ __forceinline__ void fused_finish1(const StepArgs<T>& a, T* F, LinkRec<T>* st, uint32_t* tg,
                                               const Pop<T>& p, uint32_t fl, uint32_t j0, int rr, int cc,
                                               bool in_tile, int W, int P)
 {
@@ -500,18 +542,16 @@ __device__ __forceinline__ void fused_finish1(const StepArgs<T>& a, T* F, const 
     F[7 * P + idx] = o.h7;
     F[8 * P + idx] = o.h8;
     if (in_tile && fl) {
-        for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
+        LinkRec<T>* sp = st + j0;
+        uint32_t* tp = tg + j0;
+        const DiffuseSite<T> b = diffuse_base<T, NODE>(o.dr, o.rho, o.u2);
+        for_links(fl, p, o, [&](int d, uint32_t j, T gb, T hi, T hb, T w, T cu) {
             // c_d and the unknown direction i = opposite(d)
             const int cx = (d == 1 || d == 5 || d == 8) ? 1 : ((d == 3 || d == 6 || d == 7) ? -1 : 0);
             const int cy = (d == 2 || d == 5 || d == 6) ? 1 : ((d == 4 || d == 7 || d == 8) ? -1 : 0);
             const int i = (d <= 4) ? ((d + 1) & 3) + 1 : ((d - 3) & 3) + 5;
-            const uint32_t j = j0 + rank_of(fl, d);
-            st.gb[j] = gb;
-            st.hi[j] = hi;
-            st.hb[j] = hb;
-            st.rho[j] = o.rho;
-            st.dif[j] = diffuse_term<T, NODE>(w, o.dr, o.rho, cu, o.u2);
-            tg[j] = static_cast<uint32_t>(i * P + (rr + cy) * W + (cc + cx));
+            sp[j] = LinkRec<T>{gb, hi, hb, o.rho, diffuse_term<T, NODE>(w, b, cu)};
+            tp[j] = static_cast<uint32_t>(i * P + (rr + cy) * W + (cc + cx));
         });
     }
 }
@@ -540,10 +580,8 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
     constexpr int NW1 = R / RPW;  // step-1 row waves; wave NW1 takes the halo columns
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* F = reinterpret_cast<T*>(lds_raw);  // [9][R][W] post-collision values of step 1
-    T* stg = F + 9 * P;                    // [5][lds_links] link operands (step 1, then step 2)
-    const LinkStage<T> st{stg, stg + a.lds_links, stg + 2 * a.lds_links, stg + 3 * a.lds_links,
-                          stg + 4 * a.lds_links};
-    uint32_t* tg = reinterpret_cast<uint32_t*>(stg + 5 * a.lds_links);   // [lds_links] F slot of each link
+    LinkRec<T>* st = reinterpret_cast<LinkRec<T>*>(F + 9 * P);  // [lds_links] link operands (step 1, then 2)
+    uint32_t* tg = reinterpret_cast<uint32_t*>(st + a.lds_links);     // [lds_links] F slot of each link
     uint32_t* j0s = tg + a.lds_links;                                     // [TY][64] first staging slot
     uint8_t* fls = reinterpret_cast<uint8_t*>(j0s + TY * kFuseTX);        // [TY][64] flag bytes
 
@@ -596,7 +634,15 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             const uint32_t ym = (y == 0) ? g.ny - 1 : y - 1, yp = (y + 1 == g.ny) ? 0 : y + 1;
             const uint64_t row = uint64_t(y) * g.nx;
             const uint32_t x = x0 + lane;
+            const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
             fl[h] = ld_at(g.flags + row, x);
+            p[h] = pull_planes(a.src.pop, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x, xm, xp);
+        }
+#pragma unroll
+        for (int h = 0; h < RPW; ++h) {
+            const int rr = wave * RPW + h;
+            const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
+            const uint64_t row = uint64_t(y) * g.nx;
             const uint32_t nlink = (fl[h] != kSolid) ? static_cast<uint32_t>(__popc(fl[h])) : 0u;
             const uint32_t kb = static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk]);
             k0[h] = kb + wave_prefix4(nlink);
@@ -611,13 +657,10 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
                 j0s[(rr - 1) * kFuseTX + lane] = j0[h];
                 fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(fl[h]);
             }
-            if (fl[h] != kSolid) {
-                const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
-                p[h] = pull_row(a.src.pop, a.src.link, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x, xm, xp,
-                                fl[h], k0[h]);
-                if constexpr (RPW == 1)
+            if (fl[h] != kSolid && fl[h] != 0u) pull_links(p[h], a.src.link, fl[h], k0[h]);
+            if constexpr (RPW == 1)
+                if (fl[h] != kSolid)
                     fused_finish1<T, NODE>(a, F, st, tg, p[h], fl[h], j0[h], rr, lane + 1, rr >= 1 && rr <= TY, W, P);
-            }
         }
         if constexpr (RPW > 1) {
 #pragma unroll
@@ -653,9 +696,9 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
     __syncthreads();
 
     // the boundary values of step 1, link-parallel, into the LDS slots of the solid neighbours
-    if (has1) F[tg[tid]] = link_value(w1, st.gb[tid], st.hi[tid], st.hb[tid], st.rho[tid], st.dif[tid]);
+    if (has1) F[tg[tid]] = link_value(w1, st[tid]);
     for (uint32_t jj = has1 ? tid + NT : tid; jj < total; jj += NT)
-        F[tg[jj]] = link_value(c, link_of(jj), st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
+        F[tg[jj]] = link_value(c, link_of(jj), st[jj]);
     __syncthreads();
 
     // step 2: wave w takes tile rows w RPW .. w RPW + RPW - 1, pulling from LDS (with several rows
@@ -698,17 +741,14 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             st_at(dst + 7 * ps, ox, o.h7);
             st_at(dst + 8 * ps, ox, o.h8);
             if (fl) {
-                const uint32_t j0 = j0s[r * kFuseTX + lane];
-                for_links(fl, p, o, [&](int d, T gb, T hi, T hb, T w, T cu) {
-                    const uint32_t j = j0 + rank_of(fl, d);
-                    st.gb[j] = gb;
-                    st.hi[j] = hi;
-                    st.hb[j] = hb;
-                    st.rho[j] = o.rho;
-                    st.dif[j] = diffuse_term<T, NODE>(w, o.dr, o.rho, cu, o.u2);
+                LinkRec<T>* sp = st + j0s[r * kFuseTX + lane];
+                const DiffuseSite<T> b = diffuse_base<T, NODE>(o.dr, o.rho, o.u2);
+                for_links(fl, p, o, [&](int, uint32_t rank, T gb, T hi, T hb, T w, T cu) {
+                    sp[rank] = LinkRec<T>{gb, hi, hb, o.rho, diffuse_term<T, NODE>(w, b, cu)};
                 });
             }
-        } else if (store_line) {
+        }
+        if (fl == kSolid && store_line) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) st_at(dst + i * ps, ox, T(0));
         }
@@ -733,10 +773,10 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
     }
     __syncthreads();
     // the tile's boundary values of step 2, link-parallel over its rows' contiguous link ranges
-    if (has1) a.dst.link[k1] = link_value(w1, st.gb[tid], st.hi[tid], st.hb[tid], st.rho[tid], st.dif[tid]);
+    if (has1) a.dst.link[k1] = link_value(w1, st[tid]);
     for (uint32_t jj = has1 ? tid + NT : tid; jj < total; jj += NT) {
         const uint32_t k = link_of(jj);
-        a.dst.link[k] = link_value(c, k, st.gb[jj], st.hi[jj], st.hb[jj], st.rho[jj], st.dif[jj]);
+        a.dst.link[k] = link_value(c, k, st[jj]);
     }
 }
 
