@@ -231,6 +231,34 @@ __device__ __forceinline__ void pull_links(Pop<T>& p, const T* __restrict__ lnk,
     if (has_link(f, 6)) p.g8 = lk[rank_of(f, 6)];
 }
 
+// The wall populations of a wavefront whose 64 sites are one chunk, whose links are entries
+// [kb, kb + n) of the link array in site order.  Lane i holds entry kb + i (i < 64), loaded along with
+// the plane values (lv); a site whose first link is kb + rel0 then takes each of its entries from the
+// owning lane with a cross-lane permute, done once per link direction that some site of the wave has.
+// Entries past the first 64 of the chunk are loaded directly.
+template <typename T>
+__device__ __forceinline__ void pull_links_row(Pop<T>& p, T lv, const T* __restrict__ lnk, uint32_t fl, uint32_t rel0,
+                                               uint32_t k0)
+{
+    const bool fluid = fl != kSolid;
+    auto take = [&](int d, T& gv) __attribute__((always_inline)) {
+        const bool mine = fluid && has_link(fl, d);
+        if (__ballot(mine)) {
+            const uint32_t rel = rel0 + rank_of(fl, d);
+            const T v = __shfl(lv, static_cast<int>(rel & 63u));
+            if (mine) gv = (rel < 64u) ? v : lnk[k0 + rank_of(fl, d)];
+        }
+    };
+    take(3, p.g1);  // from (x-1, y)
+    take(4, p.g2);  // from (x, y-1)
+    take(1, p.g3);  // from (x+1, y)
+    take(2, p.g4);  // from (x, y+1)
+    take(7, p.g5);  // from (x-1, y-1)
+    take(8, p.g6);  // from (x+1, y-1)
+    take(5, p.g7);  // from (x+1, y+1)
+    take(6, p.g8);  // from (x-1, y+1)
+}
+
 // Density deviation and half-force velocity (Eq. (FluidMacr)) accumulated in fp64, for the
 // residual, the recorded velocity and the moments output.
 template <typename T>
@@ -625,8 +653,9 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
         // rows -1 and TY are the halo rows).  Each row of a wave is one chunk of one lattice row,
         // so rows and chunks are wave-uniform.  With several rows per wave all are pulled before
         // any is collided; with one, pull and collision stay together (fewer live registers).
-        uint32_t fl[RPW], k0[RPW], j0[RPW];
+        uint32_t fl[RPW], k0[RPW], j0[RPW], kb[RPW];
         Pop<T> p[RPW];
+        T lv[RPW];
 #pragma unroll
         for (int h = 0; h < RPW; ++h) {
             const int rr = wave * RPW + h;
@@ -635,17 +664,21 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             const uint64_t row = uint64_t(y) * g.nx;
             const uint32_t x = x0 + lane;
             const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
+            const uint32_t c = static_cast<uint32_t>((row + x0) / kChunk);
+            kb[h] = static_cast<uint32_t>(g.chunk_base[c]);
+            [[maybe_unused]] const uint32_t nrow = static_cast<uint32_t>(g.chunk_base[c + 1]) - kb[h];
             fl[h] = ld_at(g.flags + row, x);
             p[h] = pull_planes(a.src.pop, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x, xm, xp);
+            // one row per wave (fp64): the row's link entries are fetched with the planes; with two
+            // rows per wave (fp32) the extra registers would cost a resident block, so each site
+            // loads its own entries once its link offset is known
+            if constexpr (RPW == 1) lv[h] = (static_cast<uint32_t>(lane) < nrow) ? a.src.link[kb[h] + lane] : T(0);
         }
 #pragma unroll
         for (int h = 0; h < RPW; ++h) {
             const int rr = wave * RPW + h;
-            const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
-            const uint64_t row = uint64_t(y) * g.nx;
             const uint32_t nlink = (fl[h] != kSolid) ? static_cast<uint32_t>(__popc(fl[h])) : 0u;
-            const uint32_t kb = static_cast<uint32_t>(g.chunk_base[(row + x0) / kChunk]);
-            k0[h] = kb + wave_prefix4(nlink);
+            k0[h] = kb[h] + wave_prefix4(nlink);
             j0[h] = 0;
             if (rr >= 1 && rr <= TY) {
                 uint32_t off = 0;  // staging offset of this tile row: the links of the tile rows above
@@ -653,11 +686,14 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
                     const uint32_t cq = ((y0 + q) * g.nx + x0) / kChunk;
                     off += static_cast<uint32_t>(g.chunk_base[cq + 1] - g.chunk_base[cq]);
                 }
-                j0[h] = off + (k0[h] - kb);
+                j0[h] = off + (k0[h] - kb[h]);
                 j0s[(rr - 1) * kFuseTX + lane] = j0[h];
                 fls[(rr - 1) * kFuseTX + lane] = static_cast<uint8_t>(fl[h]);
             }
-            if (fl[h] != kSolid && fl[h] != 0u) pull_links(p[h], a.src.link, fl[h], k0[h]);
+            if constexpr (RPW == 1)
+                pull_links_row(p[h], lv[h], a.src.link, fl[h], k0[h] - kb[h], k0[h]);
+            else if (fl[h] != kSolid && fl[h] != 0u)
+                pull_links(p[h], a.src.link, fl[h], k0[h]);
             if constexpr (RPW == 1)
                 if (fl[h] != kSolid)
                     fused_finish1<T, NODE>(a, F, st, tg, p[h], fl[h], j0[h], rr, lane + 1, rr >= 1 && rr <= TY, W, P);
