@@ -537,16 +537,16 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs<T> a)
 
 // ------------------------------------------------------- two time steps per launch (fused)
 //
-// Temporal blocking: a block of 64 (TY + 3) threads owns a tile of 64 x TY sites (64 = one chunk).
-// Step 1 runs on the tile and a one-site halo around it, one wave per row and one more wave for
-// the two halo columns: its sites pull from the global planes and link array of time t, collide,
-// and leave their nine post-collision values in LDS; the tile's sites also evaluate their boundary
-// values and leave each in the LDS slot of the solid neighbour x + c_d, which is exactly where
-// step 2 pulls it.  Step 2 runs on the tile only, pulling from LDS, and stores time t + 2 to the
-// global planes (whole lines) and its boundary values to the link array (link-parallel over the
-// tile rows' contiguous link ranges, as in step_tile).  Each site's arithmetic
-// is that of step_tile (same collide / link_value / diffuse_term), so two fused steps give the
-// bits of two single steps.  Needs nx % 64 == 0 and ny % TY == 0.
+// Temporal blocking: a block owns a tile of 64 x TY sites (64 = one chunk).  Step 1 runs on the
+// tile and a one-site halo around it, RPW rows per wave and one more wave for the two halo columns:
+// its sites pull from the global planes and link array of time t, collide, and leave their nine
+// post-collision values in LDS; the tile's sites also stage the operands of their wall links, and
+// after a barrier one link-parallel pass leaves each boundary value in the LDS slot of the solid
+// neighbour x + c_d, which is exactly where step 2 pulls it.  Step 2 runs on the tile only, pulling
+// from LDS, and stores time t + 2 to the global planes (whole lines) and its boundary values to the
+// link array (link-parallel over the tile rows' contiguous link ranges, as in step_tile).  Each
+// site's arithmetic is that of step_tile (same collide / link_value / diffuse_term), so two fused
+// steps give the bits of two single steps.  Needs nx % 64 == 0 and ny % TY == 0.
 
 // Step 1 of one site whose nine incoming populations p have been pulled: collision, the nine
 // post-collision values into LDS row rr, column cc, and (tile sites only) the operands of each of
