@@ -214,9 +214,10 @@ lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block);
  * step.  2: one launch advances two steps on 64 x rows tiles, keeping the intermediate time level
  * in LDS (temporal blocking); this halves the HBM traffic per step, and lbm_step then runs pairs
  * of steps and a single step for an odd remainder.  Results are bit-identical either way.  The
- * default is 2 where the lattice tiles, else 1.  rows: tile rows (4 or 8; 0 = the largest that
- * fits).  LBM_E_INVAL if 2 is asked and nx is not a multiple of 64, ny not a multiple of rows, or a
- * tile's wall links do not fit the LDS staging area. */
+ * default is 2 where the lattice tiles, else 1.  rows: tile rows (4 or 8; 0 = the default: 4 for
+ * fp32 storage and 8 for fp64, or the other where only that one fits).  LBM_E_INVAL if 2 is asked
+ * and nx is not a multiple of 64, ny not a multiple of rows, or a tile's wall links do not fit the
+ * LDS staging area. */
 lbm_status lbm_set_fusion(lbm_ctx *ctx, int32_t steps_per_launch, int32_t rows);
 
 /* Average duration in milliseconds of the step kernel launches of the last lbm_step call,

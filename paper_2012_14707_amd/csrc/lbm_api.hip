@@ -9,6 +9,7 @@
 #include <initializer_list>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -78,6 +79,13 @@ struct lbm_ctx {
                 best = std::max(best, sum);
             }
         return best;
+    }
+    // Tile heights of the two-step kernel in order of preference: fp32 blocks (two rows per wave)
+    // are fastest with 4-row tiles, whose small blocks fit eight to a CU; fp64 with 8 rows, where
+    // the LDS tile caps the blocks per CU anyway and taller tiles recompute fewer halo rows.
+    std::array<int, 2> fusion_rows_order() const
+    {
+        return fp32() ? std::array<int, 2>{4, 8} : std::array<int, 2>{8, 4};
     }
     // Whether the two-step kernel can run with `rows` tile rows, and its LDS link slots.
     bool fusion_fits(int rows, uint32_t* links) const
@@ -253,7 +261,7 @@ lbm_status lbm_create(const lbm_params* p, const uint8_t* solid, const lbm_link*
     }
     // two time steps per launch by default where the lattice tiles into 64 x rows blocks (half the
     // HBM traffic per step; faster in both precisions)
-    for (int rows : {8, 4}) {
+    for (int rows : c->fusion_rows_order()) {
         uint32_t links = 0;
         if (c->fusion_fits(rows, &links)) {
             c->fuse = 2;
@@ -505,7 +513,8 @@ lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows)
     }
     if (steps_per_launch != 2) return fail(LBM_E_INVAL, "steps per launch must be 1 or 2, not %d", steps_per_launch);
     if (rows != 0 && rows != 4 && rows != 8) return fail(LBM_E_INVAL, "tile rows %d not one of 4, 8", rows);
-    std::initializer_list<int> cand = rows ? std::initializer_list<int>{rows} : std::initializer_list<int>{8, 4};
+    const std::array<int, 2> order = c->fusion_rows_order();
+    const std::array<int, 2> cand = rows ? std::array<int, 2>{rows, rows} : order;
     for (int r : cand) {
         uint32_t links = 0;
         if (c->fusion_fits(r, &links)) {
