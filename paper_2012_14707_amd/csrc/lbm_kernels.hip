@@ -737,8 +737,7 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
         F[tg[jj]] = link_value(c, link_of(jj), st[jj]);
     __syncthreads();
 
-    // step 2: wave w takes tile rows w RPW .. w RPW + RPW - 1, pulling from LDS (with several rows
-    // per wave, all rows' LDS loads are issued first)
+    // step 2: pulling from LDS (with several rows per wave, all rows' LDS loads are issued first)
     auto load2 = [&](int r, Pop<T>& p) __attribute__((always_inline)) {
         const int idx = (r + 1) * W + lane + 1;
         p.g0 = F[idx];
@@ -789,22 +788,24 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             for (int i = 0; i < 9; ++i) st_at(dst + i * ps, ox, T(0));
         }
     };
-    if (wave < TY / RPW) {
-        if constexpr (RPW == 1) {
+    // one tile row per wave when the block has a wave for every row, else RPW rows per wave
+    constexpr int RPW2 = (TY <= NW1 + 1) ? 1 : RPW;
+    if (wave < TY / RPW2) {
+        if constexpr (RPW2 == 1) {
             const uint32_t fl = fls[wave * kFuseTX + lane];
             Pop<T> p;
             if (fl != kSolid) load2(wave, p);
             finish2(wave, fl, p);
         } else {
-            uint32_t fl[RPW];
-            Pop<T> p[RPW];
+            uint32_t fl[RPW2];
+            Pop<T> p[RPW2];
 #pragma unroll
-            for (int h = 0; h < RPW; ++h) {
-                fl[h] = fls[(wave * RPW + h) * kFuseTX + lane];
-                if (fl[h] != kSolid) load2(wave * RPW + h, p[h]);
+            for (int h = 0; h < RPW2; ++h) {
+                fl[h] = fls[(wave * RPW2 + h) * kFuseTX + lane];
+                if (fl[h] != kSolid) load2(wave * RPW2 + h, p[h]);
             }
 #pragma unroll
-            for (int h = 0; h < RPW; ++h) finish2(wave * RPW + h, fl[h], p[h]);
+            for (int h = 0; h < RPW2; ++h) finish2(wave * RPW2 + h, fl[h], p[h]);
         }
     }
     __syncthreads();
