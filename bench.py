@@ -314,16 +314,21 @@ def main():
             "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": None,
         },
+        # kernel time per time step (a two-step launch counts as two steps); roofline.achieved is the
+        # algorithmic bytes of the launch's steps over the launch's duration
         "kernel_avg_ms": round(head["kernel_avg_ms"], 5),
-        "bytes_per_launch": head["bytes_per_step"],
+        "steps_per_launch": head["steps_per_launch"],
+        "bytes_per_step": head["bytes_per_step"],
+        "bytes_per_launch": head["bytes_per_step"] * head["steps_per_launch"],
         "mflups": round(head["mflups"], 1),
     }
     counted = counted_traffic(head_name, args.n)
-    if counted:
+    if counted and counted["steps_per_dispatch"] == head["steps_per_launch"]:
         total = counted["read_bytes"] + counted["write_bytes"]
-        line["roofline"]["traffic"] = round(total / (head["kernel_avg_ms"] * 1e-3) / 1e9, 1)
+        per_launch_ms = head["kernel_avg_ms"] * counted["steps_per_dispatch"]
+        line["roofline"]["traffic"] = round(total / (per_launch_ms * 1e-3) / 1e9, 1)
         line["hbm_counters"] = {"read_bytes": round(counted["read_bytes"]), "write_bytes": round(counted["write_bytes"]),
-                                "source": counted["source"]}
+                                "steps_per_dispatch": counted["steps_per_dispatch"], "source": counted["source"]}
     if "fp64" in results and head_name != "fp64":
         r = results["fp64"]
         line["fp64"] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
@@ -333,7 +338,7 @@ def main():
                         "achieved_gbs_per_step_bytes": round(r["achieved_gbs"], 1),
                         "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
         c64 = counted_traffic("fp64", args.n)
-        if c64:
+        if c64 and c64["steps_per_dispatch"] == r["steps_per_launch"]:
             per_launch_ms = r["kernel_avg_ms"] * c64["steps_per_dispatch"]
             line["fp64"]["traffic"] = round((c64["read_bytes"] + c64["write_bytes"]) / (per_launch_ms * 1e-3) / 1e9, 1)
             line["fp64"]["hbm_counters"] = {"read_bytes": round(c64["read_bytes"]),
