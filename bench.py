@@ -214,6 +214,25 @@ def warm_start(n_eval=40, tol=1e-8):
     return {k: (round(v, 4) if isinstance(v, float) and k != "tol" else v) for k, v in out.items()}
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Read + write GB/s of a plain device-to-device copy (the practical streaming ceiling that the
+    step kernel's counted traffic is compared with), timed with HIP events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 8.0 * n / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(problem, steps=2):
     """The oracle as it stands on this host's cores: `steps` steps of the full lattice."""
     import oracle
@@ -322,6 +341,9 @@ def main():
         "bytes_per_launch": head["bytes_per_step"] * head["steps_per_launch"],
         "mflups": round(head["mflups"], 1),
     }
+    cb = copy_bandwidth()
+    line["copy_bandwidth"] = {"gbs": round(cb, 1), "workload": "1 GiB device copy, read + write bytes",
+                              "achieved_over_copy": round(head["achieved_gbs"] / cb, 4)}
     counted = counted_traffic(head_name, args.n)
     if counted and counted["steps_per_dispatch"] == head["steps_per_launch"]:
         total = counted["read_bytes"] + counted["write_bytes"]
@@ -329,6 +351,7 @@ def main():
         line["roofline"]["traffic"] = round(total / (per_launch_ms * 1e-3) / 1e9, 1)
         line["hbm_counters"] = {"read_bytes": round(counted["read_bytes"]), "write_bytes": round(counted["write_bytes"]),
                                 "steps_per_dispatch": counted["steps_per_dispatch"], "source": counted["source"]}
+        line["copy_bandwidth"]["traffic_over_copy"] = round(line["roofline"]["traffic"] / cb, 4)
     if "fp64" in results and head_name != "fp64":
         r = results["fp64"]
         line["fp64"] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
