@@ -233,8 +233,23 @@ def copy_bandwidth(mib=1024, reps=10):
     return 8.0 * n / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(problem, steps=2):
-    """The oracle as it stands on this host's cores: `steps` steps of the full lattice."""
+_SINGLE_THREAD = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_2012_14707_amd import geometry as G
+pb = G.throughput_config3(n={n}, seed=0)
+o = oracle.Oracle(pb["params"], pb["solid"], pb["links"])
+t = time.perf_counter()
+o.step(1)
+print(pb["solid"].size / (time.perf_counter() - t) / 1e6)
+"""
+
+
+def cpu_baseline(problem, steps=2, single_thread=True):
+    """The oracle as it stands on this host's cores: `steps` steps of the full lattice; and one step
+    with a single OpenMP thread, in a child process (the thread count is read at library load)."""
+    import subprocess
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -244,9 +259,17 @@ def cpu_baseline(problem, steps=2):
     t2 = time.perf_counter()
     n_sites = problem["solid"].size
     del ora
-    return dict(value=n_sites * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"{steps} full steps of the 4096x4096 lattice (x87 extended precision, OpenMP over sites); "
-                       f"setup {t1 - t0:.1f} s excluded")
+    out = dict(value=n_sites * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+               sample=f"{steps} full steps of the 4096x4096 lattice (x87 extended precision, OpenMP over sites); "
+                      f"setup {t1 - t0:.1f} s excluded")
+    if single_thread:
+        code = _SINGLE_THREAD.format(root=ROOT, n=problem["solid"].shape[0])
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            out["single_thread"] = {"value": float(r.stdout.strip().splitlines()[-1]), "unit": "MLUPS",
+                                    "sample": "1 full step of the same lattice, one OpenMP thread"}
+    return out
 
 
 def main():

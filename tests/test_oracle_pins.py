@@ -507,3 +507,30 @@ def test_wall_fit_inclined_channel():
         err[name] = float(np.max(np.abs(ux * c + uy * s - ana)[fl]) / uc)
     assert err["wall_fit"] < 0.8 * err["wall_paper"], err
     assert err["wall_fit"] < 1.1 * err["node"], err
+
+
+def test_oracle_bitwise_across_thread_counts():
+    """The oracle's parallel loops are independent per site (no parallel reductions), so its state
+    is bitwise the same for any OpenMP thread count; checked in fresh processes with 1 and 4
+    threads (the thread count is read when the library loads)."""
+    import hashlib
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import hashlib, numpy as np\n"
+        "import oracle\n"
+        "from paper_2012_14707_amd import geometry as G\n"
+        "pb = G.random_cylinders(n=64, porosity=0.7, rmin=5, rmax=9, seed=2, kn=0.05, h=14.0, ax=1e-6)\n"
+        "o = oracle.Oracle(pb['params'], pb['solid'], pb['links'])\n"
+        "o.step(40)\n"
+        "print(hashlib.sha256(np.ascontiguousarray(o.get_f()).tobytes()).hexdigest())\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = []
+    for threads in ("1", "4"):
+        env = dict(os.environ, OMP_NUM_THREADS=threads, PYTHONPATH=root)
+        r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr
+        out.append(r.stdout.strip().splitlines()[-1])
+    assert out[0] == out[1] and len(out[0]) == 64, out
