@@ -33,7 +33,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_precision(problem, precision, steps, warmup, block):
+def time_precision(problem, precision, steps, warmup, block, repeats=4):
+    import statistics
     import torch
     from paper_2012_14707_amd import lbm
 
@@ -43,24 +44,30 @@ def time_precision(problem, precision, steps, warmup, block):
     lat.step(warmup)
     lat.residual()
     lat.set_timing(True)
-    kernel_ms = 0.0
-    kernel_steps = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    done = 0
-    while done < steps:
-        k = min(CHECK_EVERY, steps - done)
-        lat.step(k)
-        res, mass = lat.residual()   # synchronises
-        ms, n = lat.last_step_ms()
-        kernel_ms += ms
-        kernel_steps += n
-        done += k
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+
+    def timed_block():
+        kernel_ms, kernel_steps = 0.0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        res = mass = None
+        while done < steps:
+            k = min(CHECK_EVERY, steps - done)
+            lat.step(k)
+            res, mass = lat.residual()   # synchronises
+            ms, n = lat.last_step_ms()
+            kernel_ms += ms
+            kernel_steps += n
+            done += k
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, kernel_ms / kernel_steps, res, mass
+
+    # the reported figures come from the first timed block of exactly `steps` steps; the repeats
+    # that follow only show the spread
+    wall, kernel_avg_ms, res, mass = timed_block()
+    spread = [wall / steps * 1e3] + [timed_block()[0] / steps * 1e3 for _ in range(repeats)]
     lat.set_timing(False)
     ms_per_step = wall / steps * 1e3
-    kernel_avg_ms = kernel_ms / kernel_steps
     out = dict(
         ms_per_step=ms_per_step,
         mlups=info["n_sites"] / (ms_per_step * 1e3),
@@ -77,6 +84,8 @@ def time_precision(problem, precision, steps, warmup, block):
         tau_s=info["tau_s"],
         tau_q=info["tau_q"],
         steps_per_launch=info["steps_per_launch"],
+        repeats={"blocks": len(spread), "median_ms_per_step": round(statistics.median(spread), 5),
+                 "min_ms_per_step": round(min(spread), 5), "max_ms_per_step": round(max(spread), 5)},
     )
     lat.close()
     return out
@@ -359,6 +368,7 @@ def main():
         # kernel time per time step (a two-step launch counts as two steps); roofline.achieved is the
         # algorithmic bytes of the launch's steps over the launch's duration
         "kernel_avg_ms": round(head["kernel_avg_ms"], 5),
+        "timed_blocks": head["repeats"],
         "steps_per_launch": head["steps_per_launch"],
         "bytes_per_step": head["bytes_per_step"],
         "bytes_per_launch": head["bytes_per_step"] * head["steps_per_launch"],
@@ -382,7 +392,7 @@ def main():
                         # per-step algorithmic bytes over the per-step kernel time; with two steps per
                         # launch the kernel moves about half of them, so this can exceed what HBM gives
                         "achieved_gbs_per_step_bytes": round(r["achieved_gbs"], 1),
-                        "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+                        "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "timed_blocks": r["repeats"]}
         c64 = counted_traffic("fp64", args.n)
         if c64 and c64["steps_per_dispatch"] == r["steps_per_launch"]:
             per_launch_ms = r["kernel_avg_ms"] * c64["steps_per_dispatch"]
