@@ -259,6 +259,30 @@ __device__ __forceinline__ void pull_links_row(Pop<T>& p, T lv, const T* __restr
     take(6, p.g8);  // from (x-1, y+1)
 }
 
+// The wall populations of a site whose chunk's first 64 link entries have been copied to LDS
+// (stage[j] = entry kb + j); rel0 is the site's first link relative to kb.  Entries past the first
+// 64 of the chunk are loaded directly.
+template <typename T>
+__device__ __forceinline__ void pull_links_staged(Pop<T>& p, const T* stage, const T* __restrict__ lnk, uint32_t fl,
+                                                  uint32_t rel0, uint32_t k0)
+{
+    auto take = [&](int d, T& gv) __attribute__((always_inline)) {
+        if (has_link(fl, d)) {
+            const uint32_t rel = rel0 + rank_of(fl, d);
+            gv = stage[rel & 63u];  // an LDS read in every case (a shared load would be a flat one)
+            if (rel >= 64u) gv = lnk[k0 + rank_of(fl, d)];
+        }
+    };
+    take(3, p.g1);  // from (x-1, y)
+    take(4, p.g2);  // from (x, y-1)
+    take(1, p.g3);  // from (x+1, y)
+    take(2, p.g4);  // from (x, y+1)
+    take(7, p.g5);  // from (x-1, y-1)
+    take(8, p.g6);  // from (x+1, y-1)
+    take(5, p.g7);  // from (x+1, y+1)
+    take(6, p.g8);  // from (x-1, y+1)
+}
+
 // Density deviation and half-force velocity (Eq. (FluidMacr)) accumulated in fp64, for the
 // residual, the recorded velocity and the moments output.
 template <typename T>
@@ -653,26 +677,44 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
         // rows -1 and TY are the halo rows).  Each row of a wave is one chunk of one lattice row,
         // so rows and chunks are wave-uniform.  With several rows per wave all are pulled before
         // any is collided; with one, pull and collision stay together (fewer live registers).
-        uint32_t fl[RPW], k0[RPW], j0[RPW], kb[RPW];
+        uint32_t fl[RPW], k0[RPW], j0[RPW], kb[RPW], nrow[RPW], yr[RPW];
         Pop<T> p[RPW];
         T lv[RPW];
+        // the rows' chunk offsets come first: scalar loads, all issued before any direct LDS load
+        // (after one, the compiler no longer takes the offset table as unchanged)
 #pragma unroll
         for (int h = 0; h < RPW; ++h) {
             const int rr = wave * RPW + h;
-            const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
+            yr[h] = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
+            const uint32_t c = static_cast<uint32_t>((uint64_t(yr[h]) * g.nx + x0) / kChunk);
+            kb[h] = static_cast<uint32_t>(g.chunk_base[c]);
+            nrow[h] = static_cast<uint32_t>(g.chunk_base[c + 1]) - kb[h];
+        }
+#pragma unroll
+        for (int h = 0; h < RPW; ++h) {
+            const int rr = wave * RPW + h;
+            const uint32_t y = yr[h];
             const uint32_t ym = (y == 0) ? g.ny - 1 : y - 1, yp = (y + 1 == g.ny) ? 0 : y + 1;
             const uint64_t row = uint64_t(y) * g.nx;
             const uint32_t x = x0 + lane;
             const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
-            const uint32_t c = static_cast<uint32_t>((row + x0) / kChunk);
-            kb[h] = static_cast<uint32_t>(g.chunk_base[c]);
-            [[maybe_unused]] const uint32_t nrow = static_cast<uint32_t>(g.chunk_base[c + 1]) - kb[h];
             fl[h] = ld_at(g.flags + row, x);
             p[h] = pull_planes(a.src.pop, ps, row, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x, xm, xp);
-            // one row per wave (fp64): the row's link entries are fetched with the planes; with two
-            // rows per wave (fp32) the extra registers would cost a resident block, so each site
-            // loads its own entries once its link offset is known
-            if constexpr (RPW == 1) lv[h] = (static_cast<uint32_t>(lane) < nrow) ? a.src.link[kb[h] + lane] : T(0);
+            // the row's first 64 link entries are fetched with the planes: in fp64 (one row per
+            // wave) into a register of each lane; in fp32 straight into LDS, into this row's slots
+            // of plane 0, which only this wave writes and only after it has read them
+            if constexpr (RPW == 1) {
+                lv[h] = (static_cast<uint32_t>(lane) < nrow[h]) ? a.src.link[kb[h] + lane] : T(0);
+            } else {
+                static_assert(sizeof(T) == 4, "direct LDS staging of link entries moves one dword per lane");
+                if (static_cast<uint32_t>(lane) < nrow[h] && lane < 64)
+                    __builtin_amdgcn_global_load_lds(a.src.link + kb[h] + lane,
+                                                     (__attribute__((address_space(3))) void*)(F + rr * W + 1), 4, 0, 0);
+            }
+        }
+        if constexpr (RPW > 1) {
+            // the compiler does not track the LDS writes of the direct loads: wait for them here
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }
 #pragma unroll
         for (int h = 0; h < RPW; ++h) {
@@ -682,9 +724,15 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             j0[h] = 0;
             if (rr >= 1 && rr <= TY) {
                 uint32_t off = 0;  // staging offset of this tile row: the links of the tile rows above
-                for (int q = 0; q < rr - 1; ++q) {
-                    const uint32_t cq = ((y0 + q) * g.nx + x0) / kChunk;
-                    off += static_cast<uint32_t>(g.chunk_base[cq + 1] - g.chunk_base[cq]);
+                if constexpr (RPW == 1) {
+                    for (int q = 0; q < rr - 1; ++q) {
+                        const uint32_t cq = ((y0 + q) * g.nx + x0) / kChunk;
+                        off += static_cast<uint32_t>(g.chunk_base[cq + 1] - g.chunk_base[cq]);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 1; q < TY; ++q)
+                        if (rr - 1 == q) off = oq[q];
                 }
                 j0[h] = off + (k0[h] - kb[h]);
                 j0s[(rr - 1) * kFuseTX + lane] = j0[h];
@@ -693,7 +741,7 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             if constexpr (RPW == 1)
                 pull_links_row(p[h], lv[h], a.src.link, fl[h], k0[h] - kb[h], k0[h]);
             else if (fl[h] != kSolid && fl[h] != 0u)
-                pull_links(p[h], a.src.link, fl[h], k0[h]);
+                pull_links_staged(p[h], F + rr * W + 1, a.src.link, fl[h], k0[h] - kb[h], k0[h]);
             if constexpr (RPW == 1)
                 if (fl[h] != kSolid)
                     fused_finish1<T, NODE>(a, F, st, tg, p[h], fl[h], j0[h], rr, lane + 1, rr >= 1 && rr <= TY, W, P);
@@ -708,24 +756,35 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
             }
         }
     } else if (lane < 2 * R) {
-        // the last wave: halo columns x0 - 1 (last site of its chunk) and x0 + 64 (first of its chunk)
+        // the last wave: halo columns x0 - 1 (last site of its chunk) and x0 + 64 (first of its
+        // chunk)
         const int rr = lane >> 1, side = lane & 1;
         const uint32_t y = (rr == 0) ? (y0 == 0 ? g.ny - 1 : y0 - 1) : ((y0 + rr - 1 == g.ny) ? 0 : y0 + rr - 1);
         const uint32_t x = side ? ((x0 + kFuseTX == g.nx) ? 0 : x0 + kFuseTX) : (x0 == 0 ? g.nx - 1 : x0 - 1);
         const uint32_t s = y * g.nx + x;
+        const uint32_t xm = (x == 0) ? g.nx - 1 : x - 1, xp = (x + 1 == g.nx) ? 0 : x + 1;
+        const uint32_t ym = (y == 0) ? g.ny - 1 : y - 1, yp = (y + 1 == g.ny) ? 0 : y + 1;
         const uint32_t fl = g.flags[s];
         if (fl != kSolid) {
-            const uint32_t k0 = side ? static_cast<uint32_t>(g.chunk_base[s / kChunk])
-                                     : static_cast<uint32_t>(g.chunk_base[s / kChunk + 1]) -
-                                           static_cast<uint32_t>(__popc(fl));
-            Nbr b;
-            b.x = x;
-            b.xm = (x == 0) ? g.nx - 1 : x - 1;
-            b.xp = (x + 1 == g.nx) ? 0 : x + 1;
-            b.row = y * g.nx;
-            b.rowm = ((y == 0) ? g.ny - 1 : y - 1) * g.nx;
-            b.rowp = ((y + 1 == g.ny) ? 0 : y + 1) * g.nx;
-            const Pop<T> p = pull(a.src.pop, a.src.link, ps, s, b, fl, k0);
+            const uint32_t cb = static_cast<uint32_t>(g.chunk_base[s / kChunk + (side ? 0u : 1u)]);
+            const uint32_t k0 = side ? cb : cb - static_cast<uint32_t>(__popc(fl));
+            Pop<T> p;
+            if constexpr (sizeof(T) == 4) {
+                // the nine plane values are requested before the link entries, which wait for the
+                // chunk offset (measured faster in fp32)
+                p = pull_planes(a.src.pop, ps, uint64_t(y) * g.nx, uint64_t(ym) * g.nx, uint64_t(yp) * g.nx, x, xm, xp);
+                if (fl != 0u) pull_links(p, a.src.link, fl, k0);
+            } else {
+                // one load per population, from the plane or the link array
+                Nbr b;
+                b.x = x;
+                b.xm = xm;
+                b.xp = xp;
+                b.row = y * g.nx;
+                b.rowm = ym * g.nx;
+                b.rowp = yp * g.nx;
+                p = pull(a.src.pop, a.src.link, ps, s, b, fl, k0);
+            }
             fused_finish1<T, NODE>(a, F, st, tg, p, fl, 0, rr, side ? W - 1 : 0, false, W, P);
         }
     }

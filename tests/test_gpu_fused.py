@@ -91,3 +91,38 @@ def test_lattices_that_do_not_tile_keep_single_steps():
         lat2.set_fusion(2, 16)  # tiles have 4 or 8 rows
     with pytest.raises(lbm.LbmError):
         lat2.set_fusion(3)
+
+
+def _slits():
+    """One-site-wide periodic slits (even rows solid): every fluid site has six wall links, so each
+    64-site chunk owns 384 link entries, far more than one wave holds per chunk row."""
+    ny, nx = 16, 128
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[0::2, :] = 1
+    xs, ys, ds = G.wall_candidates(solid, 1, 1)
+    q = np.array([0.3, 0.5, 0.7])[np.arange(len(xs)) % 3]
+    links = dict(x=xs, y=ys, dir=ds, q=q, ubx=np.zeros(len(xs)), uby=np.zeros(len(xs)))
+    params = G.base_params(periodic_x=1, periodic_y=1, kn=0.05, h=20.0, ax=1e-6)
+    return dict(params=params, solid=solid, links=links, meta=dict(kind="slits"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_two_step_launch_many_links_per_chunk(precision):
+    from paper_2012_14707_amd import lbm
+    pb = _slits()
+    lk = pb["links"]
+    per_chunk = np.bincount((lk["y"].astype(np.int64) * pb["solid"].shape[1] + lk["x"]) // 64)
+    assert per_chunk.max() > 64
+    fused = lbm.Lattice(pb, precision=precision)
+    single = lbm.Lattice(pb, precision=precision)
+    assert fused.info["steps_per_launch"] == 2
+    single.set_fusion(1)
+    init = _fields(pb["solid"].shape, 5)
+    for lat in (fused, single):
+        lat.init_fields(*init)
+    for n in (37, 2, 1, 60):
+        fused.step(n)
+        single.step(n)
+        assert _same(fused, single), (precision, n)
+    assert np.isfinite(single.moments_host()[1]).all()
+    _say(f"[fused] slits {precision}: {per_chunk.max()} links per chunk, 100 steps bitwise equal")
