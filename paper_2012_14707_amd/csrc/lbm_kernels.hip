@@ -24,8 +24,10 @@
 // barrier the block's threads walk the block's contiguous link range one link per thread, load
 // the link coefficients (coalesced) and store the boundary value (coalesced).
 //
-// The kernels are bound by HBM traffic (about 1-2 flop per byte); the 9x9 moment transform is
-// applied in closed form with additions only, not as a dense contraction.
+// The single-step kernel is bound by HBM traffic (about 1-2 flop per byte).  The two-step kernel
+// moves about half the bytes per step and is bound instead by the cache lines each CU can have in
+// flight and by vector issue.  The 9x9 moment transform is applied in closed form with additions
+// only, not as a dense contraction.
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.hpp"
