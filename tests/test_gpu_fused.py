@@ -1,7 +1,7 @@
 """Two time steps per launch (temporal blocking, lbm_set_fusion): bit-identical to one step per
 launch on lattices that tile into 64 x rows blocks, for both storage precisions, every tile-row
 option, odd step counts (pairs plus a single step) and moving walls; lattices that do not tile
-keep one step per launch."""
+keep one step per launch; both readings of the diffuse term and chunks with more link entries than a wave holds are covered."""
 import sys
 
 import numpy as np
@@ -126,3 +126,27 @@ def test_two_step_launch_many_links_per_chunk(precision):
         assert _same(fused, single), (precision, n)
     assert np.isfinite(single.moments_host()[1]).all()
     _say(f"[fused] slits {precision}: {per_chunk.max()} links per chunk, 100 steps bitwise equal")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["cylinders256", "annulus128"])
+def test_two_step_launch_wall_reading(case, precision):
+    """The wall reading of the diffuse term (diffuse = wall; the annulus has moving walls): two steps
+    per launch stay bit-identical to single steps, residual included."""
+    from paper_2012_14707_amd import lbm
+    pb = _problem(case)
+    pb["params"] = dict(pb["params"], diffuse="wall")
+    fused = lbm.Lattice(pb, precision=precision)
+    single = lbm.Lattice(pb, precision=precision)
+    assert fused.info["steps_per_launch"] == 2
+    single.set_fusion(1)
+    init = _fields(pb["solid"].shape, 9)
+    for lat in (fused, single):
+        lat.init_fields(*init)
+    for n in (37, 2, 1, 60):
+        fused.step(n)
+        single.step(n)
+        assert _same(fused, single), (case, precision, n)
+        assert fused.residual() == single.residual()
+    assert np.isfinite(single.moments_host()[1]).all()
+    _say(f"[fused] {case} wall reading {precision}: 100 steps bitwise equal")
