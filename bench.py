@@ -289,8 +289,8 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "warm"], default=None,
-                    help="one storage precision of the throughput step, or only the warm-start leg")
+    ap.add_argument("--only", choices=["fp32", "fp64", "warm", "batched"], default=None,
+                    help="one storage precision of the throughput step, or only the warm-start or batched leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sweep measurement")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -321,6 +321,10 @@ def main():
     if args.only == "warm":
         log("[bench] learned warm start vs rest only")
         print(json.dumps({"metric": METRIC, "warm_start": warm_start()}), flush=True)
+        return
+    if args.only == "batched":
+        log("[bench] batched sweep only")
+        print(json.dumps({"metric": METRIC, "batched": batched_sweep()}), flush=True)
         return
     log(f"[bench] generating {args.n}x{args.n} random-cylinder lattice (seed 0)")
     t0 = time.perf_counter()
