@@ -206,3 +206,15 @@ def test_params_comparison_matches_the_paper_formulas():
     q0 = pb["links"]["q"].copy()
     hb = lbm.comparison_problem(pb, "halfway_dbb")
     assert np.all(hb["links"]["q"] == 0.5) and np.array_equal(pb["links"]["q"], q0)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with status 2 and says so, before it
+    touches a GPU."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
