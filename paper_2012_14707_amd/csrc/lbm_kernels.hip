@@ -709,7 +709,7 @@ __global__ void __launch_bounds__((step2_threads<TY, RPW>())) k_step2(const Step
                 lv[h] = (static_cast<uint32_t>(lane) < nrow[h]) ? a.src.link[kb[h] + lane] : T(0);
             } else {
                 static_assert(sizeof(T) == 4, "direct LDS staging of link entries moves one dword per lane");
-                if (static_cast<uint32_t>(lane) < nrow[h] && lane < 64)
+                if (static_cast<uint32_t>(lane) < nrow[h])
                     __builtin_amdgcn_global_load_lds(a.src.link + kb[h] + lane,
                                                      (__attribute__((address_space(3))) void*)(F + rr * W + 1), 4, 0, 0);
             }
@@ -1366,8 +1366,9 @@ hipError_t launch_step2_rows(const StepArgs<T>& a, bool write_u, bool node, hipS
 
 }  // namespace
 
-// fp64: one LDS row per step-1 wave (the LDS tile already limits a CU to two blocks); fp32: two rows
-// per wave, so that five smaller blocks share a CU and each lane has two sites' loads in flight.
+// fp64: one LDS row per step-1 wave (on 8-row tiles LDS and registers already limit a CU to two
+// blocks); fp32: two rows per wave, so that eight 4-wave blocks of 4-row tiles share a CU and each
+// lane has two sites' loads in flight.
 hipError_t launch_step2_f64(const StepArgs<double>& a, int rows, bool write_u, bool node, hipStream_t stream)
 {
     return rows == 4 ? launch_step2_rows<double, 4, 1>(a, write_u, node, stream)
