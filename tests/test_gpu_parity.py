@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the oracle, element by element.
 
-Bar (BASELINE the benchmark spec): FP64 storage within 1e-12 and FP32-shifted storage within 1e-5 of the
+Bar: FP64 storage within 1e-12 and FP32-shifted storage within 1e-5 of the
 oracle, as relative max velocity error max_x |u_gpu - u_ora| / max_x |u_ora| over fluid nodes at
 equal step counts.  Integer work (link ordering, flags, chunk offsets) is covered through these
 comparisons: a misplaced link coefficient changes the velocity at O(1) relative level.
