@@ -297,7 +297,7 @@ def main():
                     help="only run a plain device copy of this many MiB (20 times) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path; "
               "the lattice would shard by rows with a halo exchange, see the design notes.", file=sys.stderr)
         sys.exit(2)
 

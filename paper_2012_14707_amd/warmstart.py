@@ -17,8 +17,8 @@ Kozeny-Carman estimate from the mask and the link table; each is then divided by
 the training set so that the network's targets have unit RMS over fluid sites.  The network
 convolutions wrap around (the domains are doubly periodic).
 
-Run ``python -m paper_2012_14707_amd.warmstart --help`` for the data-generation / training /
-evaluation driver.
+Run ``python -m paper_2012_14707_amd.warmstart --help`` for the command line (data generation,
+training, evaluation).
 """
 import argparse
 import json
