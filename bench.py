@@ -269,7 +269,8 @@ def cpu_baseline(problem, steps=2, single_thread=True):
     n_sites = problem["solid"].size
     del ora
     out = dict(value=n_sites * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-               sample=f"{steps} full steps of the 4096x4096 lattice (x87 extended precision, OpenMP over sites); "
+               sample=f"{steps} full steps of the {problem['solid'].shape[1]}x{problem['solid'].shape[0]} lattice "
+                      "(x87 extended precision, OpenMP over sites); "
                       f"setup {t1 - t0:.1f} s excluded")
     if single_thread:
         code = _SINGLE_THREAD.format(root=ROOT, n=problem["solid"].shape[0])
