@@ -29,6 +29,9 @@ def _problem(case):
         return G.random_cylinders(n=256, porosity=0.7, rmin=8, rmax=24, seed=11, kn=0.05, h=32.0, ax=1e-6)
     if case == "cylinders128x192":
         return G.random_cylinders(n=128, ny=192, porosity=0.75, rmin=5, rmax=14, seed=4, kn=0.02, h=20.0, ax=2e-6)
+    if case == "cylinders2048x128":
+        # 32 x 32 tiles of 64 x 4: the fp32 banded tile order (4-row bands of 32 tile columns per XCD)
+        return G.random_cylinders(n=2048, ny=128, porosity=0.75, rmin=5, rmax=14, seed=5, kn=0.02, h=20.0, ax=2e-6)
     if case == "channel64":
         return G.channel(30, nx=64, gamma=0.37, kn=0.05, ax=1e-6, u_top=0.01)
     if case == "annulus128":
@@ -52,7 +55,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["cylinders256", "cylinders128x192", "channel64", "annulus128"])
+@pytest.mark.parametrize("case", ["cylinders256", "cylinders128x192", "cylinders2048x128", "channel64", "annulus128"])
 def test_two_step_launch_bitwise(case, precision):
     from paper_2012_14707_amd import lbm
     pb = _problem(case)
