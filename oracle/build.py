@@ -1,7 +1,9 @@
 """Compiles the reference oracle (test infrastructure) with the host C compiler.
 
-Two variants come out of the one source: the extended-precision oracle used by every check,
-and an fp64 build that exists only to show the rounding floor of the literal population form.
+Three variants come out of the one source: the extended-precision oracle used by most checks; a
+binary128 build for small lattices whose velocities are tiny enough that the extended build's
+rounding approaches the fp64 parity bar; and an fp64 build that exists only to show the rounding
+floor of the literal population form.
 """
 import os
 import subprocess
@@ -13,6 +15,7 @@ SRC = os.path.join(HERE, "lbm_oracle.c")
 VARIANTS = {
     "ld": ("liboracle.so", []),
     "fp64": ("liboracle_fp64.so", ["-DORACLE_FP64"]),
+    "quad": ("liboracle_quad.so", ["-DORACLE_QUAD"]),
 }
 
 
@@ -29,7 +32,7 @@ def build(force=True):
             continue
         tmp = out + ".tmp"
         cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
-               *defs, SRC, "-o", tmp, "-lm"]
+               *defs, SRC, "-o", tmp, "-lm"] + (["-lquadmath"] if "-DORACLE_QUAD" in defs else [])
         subprocess.run(cmd, check=True)
         os.replace(tmp, out)
 

@@ -31,6 +31,8 @@
  * these workloads are 1e-5 .. 1e-2, so an fp64 evaluation of the literal population form
  * carries rounding noise of order 1e-17 / 1e-5 relative to the velocity per step; the extra
  * 11 bits keep the oracle's own noise well below the parity tolerances it is used to judge.
+ * Where the velocities are smaller still (channels driven by forces near 1e-8), the same source
+ * is built with binary128 arithmetic (ORACLE_QUAD).
  *
  * Lattice units: delta_x = delta_t = 1, c = 1, c_s^2 = 1/3.
  *
@@ -49,11 +51,22 @@
 #include <stdlib.h>
 #include <string.h>
 
-#ifdef ORACLE_FP64
+#if defined(ORACLE_FP64)
 /* fp64 build, used only to show the rounding floor of the literal population form */
 typedef double real;
+#define REAL_SQRT sqrt
+#define REAL_FABS fabs
+#elif defined(ORACLE_QUAD)
+/* binary128 build (software arithmetic, about 30x slower): for small lattices whose velocities are
+ * so small (force ~1e-8) that even the extended build's population rounding reaches 1e-12 of them */
+#include <quadmath.h>
+typedef __float128 real;
+#define REAL_SQRT sqrtq
+#define REAL_FABS fabsq
 #else
 typedef long double real;
+#define REAL_SQRT sqrtl
+#define REAL_FABS fabsl
 #endif
 
 /* ---------------------------------------------------------------- D2Q9 lattice, Eq. (Eq3) */
@@ -131,9 +144,13 @@ typedef struct {
 
 /* ------------------------------------------------------------ parameter prescription */
 
+#ifdef ORACLE_QUAD
+static const real PI_L = M_PIq;
+#else
 static const real PI_L = 3.141592653589793238462643383279502884L;
+#endif
 
-static real sq6pi(void) { return sqrtl(6.0L / PI_L); }
+static real sq6pi(void) { return REAL_SQRT(6.0L / PI_L); }
 
 /* Eq. (tKnrela): tau_s = 1/2 + sqrt(6/pi) Kn H / dx, dx = 1. */
 static real tau_s_from_kn(real kn, real h) { return 0.5L + sq6pi() * kn * h; }
@@ -145,13 +162,13 @@ static real l2_poiseuille(real l1) { return 1.0L / PI_L + l1 * l1 / 2.0L; }
 /* Eq. (EqECond): upper bound on E from tau_q > 1/2. */
 static real e_max(real ts, real L1, real L2)
 {
-    return (PI_L * ts * L2 - 3.0L * sqrtl(PI_L / 6.0L) * L1) * (2.0L * ts - 1.0L) / (12.0L * ts) - 0.5L;
+    return (PI_L * ts * L2 - 3.0L * REAL_SQRT(PI_L / 6.0L) * L1) * (2.0L * ts - 1.0L) / (12.0L * ts) - 0.5L;
 }
 
 /* Eq. (NSliCoertstq): the uniform tau_q. */
 static real tau_q_uniform(real ts, real L1, real L2, real E)
 {
-    real num = (2.0L * ts - 1.0L) * (ts * sqrtl(6.0L * PI_L) * L2 - L1) - 2.0L * sq6pi() * ts * (1.0L + 6.0L * E);
+    real num = (2.0L * ts - 1.0L) * (ts * REAL_SQRT(6.0L * PI_L) * L2 - L1) - 2.0L * sq6pi() * ts * (1.0L + 6.0L * E);
     real den = 8.0L * sq6pi() * ts + 4.0L * L1 * (2.0L * ts - 1.0L);
     return num / den;
 }
@@ -404,7 +421,7 @@ static int invert_m(real out[9][9])
     for (int c = 0; c < 9; ++c) {
         int piv = c;
         for (int r = c + 1; r < 9; ++r)
-            if (fabsl(a[r][c]) > fabsl(a[piv][c])) piv = r;
+            if (REAL_FABS(a[r][c]) > REAL_FABS(a[piv][c])) piv = r;
         if (a[piv][c] == 0.0L) return -1;
         if (piv != c)
             for (int j = 0; j < 18; ++j) { real t = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = t; }
@@ -687,7 +704,7 @@ int ora_residual(const ora_ctx *o, double *residual, double *mass)
     }
     *mass = (double)m;
     if (o->steps_since_init == 0) *residual = INFINITY;
-    else *residual = (double)sqrtl(num / den);
+    else *residual = (double)REAL_SQRT(num / den);
     return ORA_OK;
 }
 
