@@ -110,8 +110,9 @@ typedef struct {
     int32_t n_nonconvex;  /* links with l outside [max(0, 2 gamma - 1), 2 gamma] (Sec. III.A) */
     int32_t precision;
     int32_t steps_per_launch; /* time steps per launch of the step kernel (see lbm_set_fusion) */
-    int64_t bytes_per_step; /* algorithmic HBM bytes of one step: 18 s per fluid node + 5 s per link
-                               + 1 flag byte per site + 4 bytes per 64-site chunk (s = 8 or 4) */
+    int64_t bytes_per_step; /* algorithmic HBM bytes of one step: 18 s per fluid node (nine populations
+                               in, nine out) + (5 + 5 s) per wall link (a 4-byte index, a direction
+                               byte, five coefficients) + 1 mask byte per site (s = 8 or 4) */
     int64_t steps;          /* steps taken since the last initialisation */
 } lbm_info;
 
@@ -220,6 +221,12 @@ lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block);
  * LDS staging area. */
 lbm_status lbm_set_fusion(lbm_ctx *ctx, int32_t steps_per_launch, int32_t rows);
 
+/* Device-to-device streaming copy of `bytes` bytes (dst, src: device memory, 16-byte aligned, bytes
+ * a multiple of 16, else LBM_E_INVAL), asynchronous on `stream` (hipStream_t, NULL = null stream).
+ * A measurement aid, not a step of the method: its bandwidth is the practical streaming ceiling
+ * that the step kernels' HBM traffic is compared with. */
+lbm_status lbm_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
 /* Average duration in milliseconds of the step kernel launches of the last lbm_step call,
  * measured with HIP events on the context's stream (0 if timing is off).  Timing is switched on
  * by lbm_set_timing(ctx, 1); it records one event pair per lbm_step call. */
@@ -290,14 +297,33 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t inst, double *rho, double *ux
 lbm_status lbm_batch_solve(lbm_batch *b, double tol, int64_t check_every, int64_t max_steps, int32_t *status,
                            int64_t *steps, double *residual);
 
+/* Replaces instance i's problem statement by *p, keeping its geometry (mask and wall links): p must
+ * have the instance's nx, ny, periodic_x, periodic_y, precision and diffuse (else LBM_E_INVAL).  The
+ * derived parameters and the per-link coefficients of Eq. (EqNewBDSC) are recomputed on the device
+ * (validation of lbm_create: LBM_E_PARAM leaves the instance unchanged); the instance is reset to
+ * rest (step count 0) and made active.  Synchronises.  Other instances are not touched. */
+lbm_status lbm_batch_set_params(lbm_batch *b, int32_t i, const lbm_params *p);
+
+/* lbm_batch_solve followed by the stability fallback for the paper's clamp rule (end of Sec. III.B:
+ * l := 0 only where Eq. (Eqexlva) gives l < -0.4, a rule the paper motivates by stability): every
+ * instance that ended LBM_DIVERGED under LBM_L_PAPER is switched to LBM_L_CLAMP_NEG (l := 0 wherever
+ * l < 0) by lbm_batch_set_params, restarted from rest and solved again alone with the same tol,
+ * check_every and max_steps.  Those instances keep LBM_L_CLAMP_NEG afterwards and report the status,
+ * step count and residual of the re-run; fell_back[i] (host, [n_inst], may be NULL) is 1 for them and
+ * 0 for every other instance, whose results are those of the first solve.  Instances are independent:
+ * a diverging instance does not change the bits of any other. */
+lbm_status lbm_batch_solve_fallback(lbm_batch *b, double tol, int64_t check_every, int64_t max_steps,
+                                    int32_t *status, int64_t *steps, double *residual, uint8_t *fell_back);
+
 lbm_status lbm_batch_set_launch(lbm_batch *b, const lbm_batch_launch *launch);
 lbm_status lbm_batch_get_launch(const lbm_batch *b, lbm_batch_launch *launch);
 
 /* Autotuner: times trial_steps steps of every candidate launch shape (block 128/256/512,
  * graph_steps 2/10/50, blocks_per_cu 0/2/4/8) on this batch with HIP events, keeps the fastest
  * and records it in the text file cache_path (NULL: no cache) under a key of (GPU architecture,
- * precision, total sites, instance count); a cached key is reused without timing.  The batch is
- * reset to rest afterwards.  Every candidate computes identical results. */
+ * precision, total sites, instance count); a cached key is reused without timing.  Either way the
+ * batch is reset to rest afterwards (lbm_batch_init_rest).  The first failing trial ends the tuning
+ * with its status.  Every candidate computes identical results. */
 lbm_status lbm_batch_tune(lbm_batch *b, const char *cache_path, int32_t trial_steps, lbm_batch_launch *chosen);
 
 /* ------------------------------------------------------------------------------------------

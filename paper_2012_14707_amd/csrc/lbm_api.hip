@@ -337,7 +337,7 @@ lbm_status lbm_get_info(const lbm_ctx* c, lbm_info* info)
     info->n_nonconvex = c->n_nonconvex;
     info->precision = c->pr.p.precision;
     const int64_t sz = c->fp32() ? 4 : 8;
-    info->bytes_per_step = 18 * sz * c->pr.n_fluid + 5 * sz * c->n_links() + int64_t(c->n()) + 4 * int64_t(c->pr.nchunks);
+    info->bytes_per_step = 18 * sz * c->pr.n_fluid + (5 + 5 * sz) * c->n_links() + int64_t(c->n());
     info->steps = c->steps;
     info->steps_per_launch = c->fuse;
     return LBM_OK;
@@ -488,6 +488,15 @@ lbm_status lbm_synchronize(lbm_ctx* c)
     if (!c) return fail(LBM_E_INVAL, "null context");
     DeviceGuard g(c->device);
     LBM_HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_stream_copy(void* dst, const void* src, int64_t bytes, void* stream)
+{
+    if (!dst || !src || bytes < 0) return fail(LBM_E_INVAL, "null pointer or negative size");
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | uint64_t(bytes)) & 15u)
+        return fail(LBM_E_INVAL, "pointers and size must be multiples of 16 bytes");
+    LBM_HIP_TRY(lbm::launch_stream_copy(dst, src, uint64_t(bytes), static_cast<hipStream_t>(stream)));
     return LBM_OK;
 }
 

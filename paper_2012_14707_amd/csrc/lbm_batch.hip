@@ -298,6 +298,43 @@ std::vector<lbm::BatchInst<T>> inst_table(const lbm_batch* b)
     return t;
 }
 
+// Uploads instance i's record of the device instance table (its physical constants).
+lbm_status upload_inst(lbm_batch* b, int32_t i)
+{
+    hipError_t e;
+    if (b->fp32) {
+        const auto t = inst_table<float>(b);
+        e = hipMemcpyAsync(static_cast<lbm::BatchInst<float>*>(b->d_inst) + i, &t[size_t(i)],
+                           sizeof(lbm::BatchInst<float>), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    } else {
+        const auto t = inst_table<double>(b);
+        e = hipMemcpyAsync(static_cast<lbm::BatchInst<double>*>(b->d_inst) + i, &t[size_t(i)],
+                           sizeof(lbm::BatchInst<double>), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
+    if (e != hipSuccess) return fail(LBM_E_HIP, "instance table upload: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// Rest state of instance i in both buffers (its plane segments, link range and u record).
+lbm_status zero_instance(lbm_batch* b, int32_t i)
+{
+    const size_t es = b->esize();
+    for (int buf = 0; buf < 2; ++buf) {
+        for (int p = 0; p < 9; ++p)
+            LBM_HIP_TRY(lbm::launch_fill_zero(static_cast<char*>(b->d_buf[buf]) + (size_t(p) * b->ps + b->off[i]) * es,
+                                              size_t(b->pr[i].n) * es, b->stream));
+        if (b->pr[i].n_links > 0)
+            LBM_HIP_TRY(lbm::launch_fill_zero(static_cast<char*>(b->d_link[buf]) + size_t(b->link_off[i]) * es,
+                                              size_t(b->pr[i].n_links) * es, b->stream));
+    }
+    for (int c = 0; c < 2; ++c)
+        LBM_HIP_TRY(lbm::launch_fill_zero(b->d_uprev + size_t(c) * b->ps + b->off[i], sizeof(double) * b->pr[i].n,
+                                          b->stream));
+    return LBM_OK;
+}
+
 std::string arch_name(int device)
 {
     hipDeviceProp_t prop;
@@ -475,7 +512,7 @@ lbm_status lbm_batch_info(const lbm_batch* b, int32_t i, lbm_info* info)
     info->n_nonconvex = b->n_nonconvex[i];
     info->precision = p.p.precision;
     const int64_t sz = int64_t(b->esize());
-    info->bytes_per_step = 18 * sz * p.n_fluid + 5 * sz * p.n_links + int64_t(p.n) + 4 * int64_t(p.nchunks);
+    info->bytes_per_step = 18 * sz * p.n_fluid + (5 + 5 * sz) * p.n_links + int64_t(p.n);
     info->steps = b->steps[i];
     return LBM_OK;
 }
@@ -657,6 +694,98 @@ lbm_status lbm_batch_solve(lbm_batch* b, double tol, int64_t check_every, int64_
     return LBM_OK;
 }
 
+lbm_status lbm_batch_set_params(lbm_batch* b, int32_t i, const lbm_params* p)
+{
+    if (!b || !p || i < 0 || i >= b->n_inst) return fail(LBM_E_INVAL, "bad batch, instance or params");
+    const lbm::Prepared& old = b->pr[i];
+    if (p->nx != old.p.nx || p->ny != old.p.ny || p->periodic_x != old.p.periodic_x ||
+        p->periodic_y != old.p.periodic_y)
+        return fail(LBM_E_INVAL, "instance %d: lattice size and periodicity cannot change", i);
+    if (p->precision != old.p.precision || p->diffuse != old.p.diffuse)
+        return fail(LBM_E_INVAL, "instance %d: precision and diffuse reading are fixed per batch", i);
+    DeviceGuard g(b->device);
+    lbm::Prepared np = old;
+    np.p = *p;
+    lbm_status st = lbm::check_params(np.p, np.g);
+    if (st != LBM_OK) return st;
+    LBM_HIP_TRY(hipStreamSynchronize(b->stream));
+    int32_t ncl = 0, nnc = 0;
+    st = lbm::precompute_links(np, b->d_coef64, b->fp32 ? b->d_coef32 : nullptr, b->link_stride(), b->link_off[i],
+                               b->stream, ncl, nnc);
+    if (st != LBM_OK) {
+        // put the previous coefficients back before reporting
+        const std::string msg = lbm_last_error();
+        int32_t a = 0, c = 0;
+        if (lbm::precompute_links(old, b->d_coef64, b->fp32 ? b->d_coef32 : nullptr, b->link_stride(),
+                                  b->link_off[i], b->stream, a, c) != LBM_OK)
+            return fail(LBM_E_HIP, "instance %d: restoring the previous coefficients failed after: %s", i,
+                        msg.c_str());
+        return fail(st, "instance %d: %s", i, msg.c_str());
+    }
+    b->pr[i] = std::move(np);
+    b->n_clamped[i] = ncl;
+    b->n_nonconvex[i] = nnc;
+    st = upload_inst(b, i);
+    if (st == LBM_OK) st = zero_instance(b, i);
+    if (st != LBM_OK) return st;
+    b->inst_cur[i] = b->cur;
+    b->steps[i] = 0;
+    b->uvalid[i] = 0;
+    b->last_res[i] = HUGE_VAL;
+    b->last_mass[i] = 0.0;
+    if (!b->active[i]) {
+        b->active[i] = 1;
+        return rebuild_tiles(b);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_solve_fallback(lbm_batch* b, double tol, int64_t check_every, int64_t max_steps, int32_t* status,
+                                    int64_t* steps_out, double* residual_out, uint8_t* fell_back)
+{
+    if (!b) return fail(LBM_E_INVAL, "null batch");
+    const size_t nn = size_t(b->n_inst);
+    std::vector<int32_t> st(nn);
+    std::vector<int64_t> steps(nn);
+    std::vector<double> res(nn);
+    lbm_status s = lbm_batch_solve(b, tol, check_every, max_steps, st.data(), steps.data(), res.data());
+    if (s != LBM_OK) return s;
+    std::vector<uint8_t> again(nn, 0);
+    bool any = false;
+    for (int32_t i = 0; i < b->n_inst; ++i)
+        if (st[i] == LBM_DIVERGED && b->pr[i].p.l_mode == LBM_L_PAPER) {
+            lbm_params p = b->pr[i].p;
+            p.l_mode = LBM_L_CLAMP_NEG;
+            s = lbm_batch_set_params(b, i, &p);
+            if (s != LBM_OK) return s;
+            again[i] = 1;
+            any = true;
+        }
+    if (any) {
+        // only the re-parametrised instances run; the others stay retired with their state
+        s = lbm_batch_set_active(b, again.data());
+        if (s != LBM_OK) return s;
+        std::vector<int32_t> st2(nn);
+        std::vector<int64_t> steps2(nn);
+        std::vector<double> res2(nn);
+        s = lbm_batch_solve(b, tol, check_every, max_steps, st2.data(), steps2.data(), res2.data());
+        if (s != LBM_OK) return s;
+        for (size_t i = 0; i < nn; ++i)
+            if (again[i]) {
+                st[i] = st2[i];
+                steps[i] = steps2[i];
+                res[i] = res2[i];
+            }
+    }
+    for (size_t i = 0; i < nn; ++i) {
+        if (status) status[i] = st[i];
+        if (steps_out) steps_out[i] = steps[i];
+        if (residual_out) residual_out[i] = res[i];
+        if (fell_back) fell_back[i] = again[i];
+    }
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l)
 {
     if (!b || !l) return fail(LBM_E_INVAL, "null argument");
@@ -690,6 +819,7 @@ lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path, int32_t trial_st
         while (in >> k >> l.block >> l.graph_steps >> l.blocks_per_cu >> ms)
             if (k == key.str()) {
                 lbm_status st = apply_launch(b, l);
+                if (st == LBM_OK) st = lbm_batch_init_rest(b);
                 if (st == LBM_OK && chosen) *chosen = b->launch;
                 return st;
             }
@@ -699,27 +829,31 @@ lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path, int32_t trial_st
     LBM_HIP_TRY(hipEventCreate(&e1));
     lbm_batch_launch best = b->launch;
     double best_ms = HUGE_VAL;
+    // one trial: capture and warm up, then time n steps; any failure ends the tuning with its status
+    auto trial = [&](const lbm_batch_launch& l) -> lbm_status {
+        if (apply_launch(b, l) != LBM_OK) return LBM_OK;  // shape not usable here (e.g. LDS): skipped
+        const int64_t n = (int64_t(trial_steps) + l.graph_steps - 1) / l.graph_steps * l.graph_steps;
+        lbm_status st = lbm_batch_step(b, l.graph_steps);
+        if (st != LBM_OK) return st;
+        LBM_HIP_TRY(hipEventRecord(e0, b->stream));
+        st = lbm_batch_step(b, n);
+        if (st != LBM_OK) return st;
+        LBM_HIP_TRY(hipEventRecord(e1, b->stream));
+        LBM_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        LBM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double per = double(ms) / double(n);
+        if (per < best_ms) {
+            best_ms = per;
+            best = l;
+        }
+        return LBM_OK;
+    };
     lbm_status status = LBM_OK;
     for (int blk : {128, 256, 512})
         for (int gs : {2, 10, 50})
-            for (int bpc : {0, 2, 4, 8}) {
-                const lbm_batch_launch l{blk, gs, bpc, 0};
-                if (apply_launch(b, l) != LBM_OK) continue;  // e.g. too many links for the LDS at this block
-                const int64_t n = (int64_t(trial_steps) + gs - 1) / gs * gs;
-                status = lbm_batch_step(b, gs);  // capture and warm up
-                if (status != LBM_OK) break;
-                if (hipEventRecord(e0, b->stream) != hipSuccess) break;
-                status = lbm_batch_step(b, n);
-                if (status != LBM_OK) break;
-                if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
-                float ms = 0;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
-                const double per = double(ms) / double(n);
-                if (per < best_ms) {
-                    best_ms = per;
-                    best = l;
-                }
-            }
+            for (int bpc : {0, 2, 4, 8})
+                if (status == LBM_OK) status = trial(lbm_batch_launch{blk, gs, bpc, 0});
     ignore(hipEventDestroy(e0));
     ignore(hipEventDestroy(e1));
     if (status != LBM_OK) return status;

@@ -19,6 +19,21 @@ const int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 bool is_set(double v) { return std::isfinite(v) && v > 0.0; }
 
+}  // namespace
+
+lbm_status fail(lbm_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
 // Global parameters of the prescription, Sec. III.B and Sec. IV.
 lbm_status derive_globals(const lbm_params& p, Globals& g)
 {
@@ -45,20 +60,18 @@ lbm_status derive_globals(const lbm_params& p, Globals& g)
     return LBM_OK;
 }
 
-}  // namespace
 
-lbm_status fail(lbm_status code, const char* fmt, ...)
+lbm_status check_params(const lbm_params& p, Globals& g)
 {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
+    if (p.l_mode < 0 || p.l_mode > LBM_L_WALL_FIT || p.r_mode < 0 || p.r_mode > LBM_R_WALL_FIT || p.diffuse < 0 ||
+        p.diffuse > 1 || p.precision < 0 || p.precision > 1)
+        return fail(LBM_E_INVAL, "mode out of range");
+    if (p.l_mode == LBM_L_WALL_FIT && p.r_mode != LBM_R_WALL_FIT)
+        return fail(LBM_E_INVAL, "LBM_L_WALL_FIT needs LBM_R_WALL_FIT");
+    if (!(p.rho0 > 0.0) || !std::isfinite(p.ax) || !std::isfinite(p.ay))
+        return fail(LBM_E_PARAM, "rho0 must be positive and a finite");
+    return derive_globals(p, g);
 }
-
-const char* last_error() { return g_last_error.c_str(); }
 
 lbm_status prepare(const lbm_params* p, const uint8_t* solid, const lbm_link* links, int64_t n_links,
                    Prepared& out)
@@ -68,15 +81,8 @@ lbm_status prepare(const lbm_params* p, const uint8_t* solid, const lbm_link* li
     const uint64_t n64 = uint64_t(p->nx) * uint64_t(p->ny);
     if (n64 >= (uint64_t(1) << 31))
         return fail(LBM_E_INVAL, "lattice of %llu sites exceeds 2^31", (unsigned long long)n64);
-    if (p->l_mode < 0 || p->l_mode > LBM_L_WALL_FIT || p->r_mode < 0 || p->r_mode > LBM_R_WALL_FIT ||
-        p->diffuse < 0 || p->diffuse > 1 || p->precision < 0 || p->precision > 1)
-        return fail(LBM_E_INVAL, "mode out of range");
-    if (p->l_mode == LBM_L_WALL_FIT && p->r_mode != LBM_R_WALL_FIT)
-        return fail(LBM_E_INVAL, "LBM_L_WALL_FIT needs LBM_R_WALL_FIT");
-    if (!(p->rho0 > 0.0) || !std::isfinite(p->ax) || !std::isfinite(p->ay))
-        return fail(LBM_E_PARAM, "rho0 must be positive and a finite");
     out.p = *p;
-    lbm_status st = derive_globals(*p, out.g);
+    lbm_status st = check_params(*p, out.g);
     if (st != LBM_OK) return st;
 
     const uint32_t nx = uint32_t(p->nx), ny = uint32_t(p->ny), n = uint32_t(n64);

@@ -57,6 +57,13 @@ struct Prepared {
     std::vector<int32_t> dir;
 };
 
+// Global parameters of the prescription (Sec. III.B, Sec. IV) from the problem statement; LBM_E_PARAM
+// if a relaxation time is not above 1/2.
+lbm_status derive_globals(const lbm_params& p, Globals& g);
+
+// Mode ranges, rho0 and the body force of *p, then derive_globals.
+lbm_status check_params(const lbm_params& p, Globals& g);
+
 // Validates the problem statement (see lbm_create in include/lbm.h) without touching the device.
 lbm_status prepare(const lbm_params* p, const uint8_t* solid, const lbm_link* links, int64_t n_links,
                    Prepared& out);

@@ -169,6 +169,8 @@ hipError_t launch_residual_batch_f32(const BatchReduceArgs<float>& a, int block,
                                      const uint32_t* tile_begin, uint32_t n_inst_active, double* out,
                                      hipStream_t stream);
 hipError_t launch_fill_zero(void* ptr, uint64_t bytes, hipStream_t stream);
+// Copies bytes (a multiple of 16; both pointers 16-byte aligned) from src to dst.
+hipError_t launch_stream_copy(void* dst, const void* src, uint64_t bytes, hipStream_t stream);
 hipError_t launch_init_fields(bool fp32, const Geo& g, void* pop, void* link, const double* rho, const double* ux,
                               const double* uy, double rho0, double ax, double ay, hipStream_t stream);
 hipError_t launch_moments(bool fp32, const Geo& g, const void* pop, const void* link, double* rho, double* ux,

@@ -1045,6 +1045,25 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint4* p, uint64_t n16)
     if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Streaming copy of n16 16-byte words (the copy that the step kernels' HBM traffic is compared with):
+// a block moves 4 x 256 consecutive words, each thread issuing its four loads before its stores.
+__global__ void __launch_bounds__(256) k_stream_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                    uint64_t n16)
+{
+    const uint64_t base = uint64_t(blockIdx.x) * 1024u + threadIdx.x;
+    uint4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = base + uint64_t(k) * 256u;
+        if (i < n16) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i = base + uint64_t(k) * 256u;
+        if (i < n16) dst[i] = v[k];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill_zero_bytes(uint8_t* p, uint64_t n)
 {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1427,6 +1446,15 @@ hipError_t launch_fill_zero(void* ptr, uint64_t bytes, hipStream_t stream)
         hipLaunchKernelGGL(k_fill_zero_bytes, dim3(ceil_div(bytes, 256)), dim3(256), 0, stream,
                            static_cast<uint8_t*>(ptr), bytes);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, uint64_t bytes, hipStream_t stream)
+{
+    const uint64_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stream_copy, dim3(ceil_div(n16, 1024)), dim3(256), 0, stream, static_cast<uint4*>(dst),
+                       static_cast<const uint4*>(src), n16);
     return hipGetLastError();
 }
 

@@ -88,6 +88,7 @@ SIGNATURES = {
     "lbm_set_stream": (C.c_int32, [_VP, _VP]),
     "lbm_synchronize": (C.c_int32, [_VP]),
     "lbm_set_launch": (C.c_int32, [_VP, C.c_int32]),
+    "lbm_stream_copy": (C.c_int32, [_VP, _VP, C.c_int64, _VP]),
     "lbm_set_timing": (C.c_int32, [_VP, C.c_int32]),
     "lbm_set_fusion": (C.c_int32, [_VP, C.c_int32, C.c_int32]),
     "lbm_last_step_ms": (C.c_int32, [_VP, _DPTR, C.POINTER(C.c_int64)]),
@@ -101,6 +102,8 @@ SIGNATURES = {
     "lbm_batch_residuals": (C.c_int32, [_VP, _VP, _VP]),
     "lbm_batch_moments": (C.c_int32, [_VP, C.c_int32, _VP, _VP, _VP, C.c_int32]),
     "lbm_batch_solve": (C.c_int32, [_VP, C.c_double, C.c_int64, C.c_int64, _VP, _VP, _VP]),
+    "lbm_batch_set_params": (C.c_int32, [_VP, C.c_int32, C.POINTER(Params)]),
+    "lbm_batch_solve_fallback": (C.c_int32, [_VP, C.c_double, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP]),
     "lbm_batch_set_launch": (C.c_int32, [_VP, C.POINTER(BatchLaunch)]),
     "lbm_batch_get_launch": (C.c_int32, [_VP, C.POINTER(BatchLaunch)]),
     "lbm_batch_tune": (C.c_int32, [_VP, C.c_char_p, C.c_int32, C.POINTER(BatchLaunch)]),
@@ -350,6 +353,7 @@ class Batch:
         _check(lib.lbm_batch_create(n, params, solids, links, counts, strm, C.byref(h)))
         self._h = h
         self.n = n
+        self.precision = precision
         self._keep = None
 
     def close(self):
@@ -401,6 +405,24 @@ class Batch:
                                          res.ctypes.data_as(C.c_void_p)))
         return [BATCH_STATUS[int(x)] for x in st], steps, res
 
+    def solve_fallback(self, tol, check_every=100, max_steps=1_000_000):
+        """lbm_batch_solve_fallback: the solve, then instances that diverged under the paper's l rule
+        re-run from rest with every negative l clamped to zero; returns (status names, steps,
+        residuals, fell_back flags)."""
+        st = np.zeros(self.n, np.int32)
+        steps = np.zeros(self.n, np.int64)
+        res = np.zeros(self.n)
+        fb = np.zeros(self.n, np.uint8)
+        _check(self._lib.lbm_batch_solve_fallback(self._h, float(tol), int(check_every), int(max_steps),
+                                                  st.ctypes.data_as(C.c_void_p), steps.ctypes.data_as(C.c_void_p),
+                                                  res.ctypes.data_as(C.c_void_p), fb.ctypes.data_as(C.c_void_p)))
+        return [BATCH_STATUS[int(x)] for x in st], steps, res, fb.astype(bool)
+
+    def set_params(self, i, params):
+        """lbm_batch_set_params: new problem statement for instance i (same geometry); resets it to rest."""
+        p = make_params(params, self.shapes[i], self.precision)
+        _check(self._lib.lbm_batch_set_params(self._h, int(i), C.byref(p)))
+
     def set_launch(self, block=256, graph_steps=10, blocks_per_cu=4):
         lb = BatchLaunch(int(block), int(graph_steps), int(blocks_per_cu), 0)
         _check(self._lib.lbm_batch_set_launch(self._h, C.byref(lb)))
@@ -425,6 +447,13 @@ def _ptr(t):
         return None
     assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
     return C.c_void_p(t.data_ptr())
+
+
+def stream_copy(dst, src, stream=None):
+    """lbm_stream_copy between two contiguous device tensors of the same size in bytes."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(load().lbm_stream_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
 
 
 def conv2d_forward(x, w, bias=None, out=None, out32=None, relu=False, periodic=False, stream=None):

@@ -30,8 +30,11 @@ def _problem(case):
     if case == "cylinders128x192":
         return G.random_cylinders(n=128, ny=192, porosity=0.75, rmin=5, rmax=14, seed=4, kn=0.02, h=20.0, ax=2e-6)
     if case == "cylinders2048x128":
-        # 32 x 32 tiles of 64 x 4: the fp32 banded tile order (4-row bands of 32 tile columns per XCD)
         return G.random_cylinders(n=2048, ny=128, porosity=0.75, rmin=5, rmax=14, seed=5, kn=0.02, h=20.0, ax=2e-6)
+    if case == "cylinders4096x256":
+        # 64 x 64 tiles of 64 x 4 (64 x 32 of 64 x 8): fp32 launches walk them in the banded per-XCD
+        # order, which remaps most tiles here (test_banded_tile_order_remaps_this_lattice)
+        return G.random_cylinders(n=4096, ny=256, porosity=0.75, rmin=5, rmax=14, seed=6, kn=0.02, h=20.0, ax=2e-6)
     if case == "channel64":
         return G.channel(30, nx=64, gamma=0.37, kn=0.05, ax=1e-6, u_top=0.01)
     if case == "annulus128":
@@ -55,7 +58,8 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["cylinders256", "cylinders128x192", "cylinders2048x128", "channel64", "annulus128"])
+@pytest.mark.parametrize("case", ["cylinders256", "cylinders128x192", "cylinders2048x128", "cylinders4096x256",
+                                  "channel64", "annulus128"])
 def test_two_step_launch_bitwise(case, precision):
     from paper_2012_14707_amd import lbm
     pb = _problem(case)
@@ -81,6 +85,34 @@ def test_two_step_launch_bitwise(case, precision):
             assert fused.residual() == single.residual()
     _say(f"[fused] {case} {precision}: {done} steps bitwise equal, residual {single.residual()[0]:.3e}")
     assert fused.info["steps"] == single.info["steps"] == done
+
+
+def _xcd_tile(b, ntiles):
+    return b if ntiles % 8 else (b % 8) * (ntiles // 8) + b // 8
+
+
+def _band_tile(b, ntiles, tiles_x):
+    """Tile of block b in the fp32 two-step launch: XCD b % 8 walks its contiguous run of tiles in
+    bands of 4 tile rows x 32 tile columns, column-major within a band."""
+    per = ntiles // 8
+    if ntiles % 8 or tiles_x % 32 or per % (4 * tiles_x):
+        return _xcd_tile(b, ntiles)
+    xg, v = b % 8, b // 8
+    band, w = v // (4 * tiles_x), v % (4 * tiles_x)
+    grp, rem = w // 128, w % 128
+    return xg * per + (band * 4 + rem // 32) * tiles_x + grp * 32 + rem % 32
+
+
+@pytest.mark.parametrize("rows", [4, 8])
+def test_banded_tile_order_remaps_this_lattice(rows):
+    """The 4096 x 256 case takes the banded order (a permutation of the tiles that differs from the
+    plain per-XCD runs for most blocks); the 2048 x 128 case does not remap any tile."""
+    for (nx, ny), want_remapped in (((4096, 256), True), ((2048, 128), False)):
+        tiles_x, ntiles = nx // 64, (nx // 64) * (ny // rows)
+        band = [_band_tile(b, ntiles, tiles_x) for b in range(ntiles)]
+        assert sorted(band) == list(range(ntiles))
+        moved = sum(t != _xcd_tile(b, ntiles) for b, t in enumerate(band))
+        assert (moved > ntiles // 2) == want_remapped, (nx, ny, rows, moved)
 
 
 def test_lattices_that_do_not_tile_keep_single_steps():
