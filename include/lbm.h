@@ -441,6 +441,17 @@ lbm_status lbm_nn_fields(const float *pred, int32_t stride, const uint8_t *solid
                          int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale, double rho0,
                          double *rho, double *ux, double *uy, int64_t *n_bad, void *stream);
 
+/* lbm_nn_fields without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results as lbm_nn_fields; its scratch (two sets of three fp64 planes and a count) lives in a fixed
+ * device array of the library, sized for nx * ny <= 262144 sites (12.6 MB, held by every GPU the
+ * library runs on until the process ends).  Larger lattices: LBM_E_INVAL before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race, so the caller serialises them.  No call here allocates or frees device memory. */
+lbm_status lbm_nn_fields_noalloc(const float *pred, int32_t stride, const uint8_t *solid, int32_t nx, int32_t ny,
+                                 int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale,
+                                 double rho0, double *rho, double *ux, double *uy, int64_t *n_bad, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -783,6 +784,83 @@ bool conv_sizes_ok(int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, 
 
 }  // namespace
 
+namespace {
+
+// Scratch of the initial-field calls: two sets of three fp64 planes, then the non-finite count.
+size_t fields_work_bytes(int64_t n) { return sizeof(double) * 6 * size_t(n) + sizeof(long long); }
+
+lbm_status fields_check(const float* pred, int32_t stride, const uint8_t* solid, int32_t nx, int32_t ny,
+                        int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale, double rho0,
+                        const double* rho, const double* ux, const double* uy, const int64_t* n_bad)
+{
+    if (!pred || !solid || !rho || !ux || !uy || !n_bad) return fail(LBM_E_INVAL, "null argument");
+    if (nx < 1 || ny < 1 || int64_t(nx) * ny > INT32_MAX / 8 || stride < 3 || smooth_iters < 0 ||
+        smooth_iters > 1000 || (periodic != 0 && periodic != 1))
+        return fail(LBM_E_INVAL, "arguments out of range");
+    if (!std::isfinite(u_scale) || !std::isfinite(rho_scale) || !std::isfinite(rho0))
+        return fail(LBM_E_INVAL, "non-finite scale");
+    return LBM_OK;
+}
+
+// Unpack, smoothing passes and the fields, with the scratch at `work` (fields_work_bytes of n).
+lbm_status fields_run(const float* pred, int32_t stride, const uint8_t* solid, int32_t nx, int32_t ny,
+                      int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale, double rho0,
+                      double* rho, double* ux, double* uy, int64_t* n_bad, void* work, hipStream_t st)
+{
+    const int n = nx * ny;
+    double* t0 = static_cast<double*>(work);
+    double* t1 = t0 + 3 * size_t(n);
+    long long* d_bad = reinterpret_cast<long long*>(t1 + 3 * size_t(n));
+    hipLaunchKernelGGL(lbm::nn::k_unpack, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, pred, stride, solid, n,
+                       t0);
+    for (int i = 0; i < smooth_iters; ++i) {
+        hipLaunchKernelGGL(lbm::nn::k_smooth, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, t0, t1, solid, nx, ny,
+                           periodic);
+        std::swap(t0, t1);
+    }
+    // k_fields writes the count (it does not accumulate), so the scratch needs no clearing
+    hipLaunchKernelGGL(lbm::nn::k_fields, dim3(1), dim3(1024), 0, st, t0, solid, n, u_scale, rho_scale, rho0, rho, ux,
+                       uy, d_bad);
+    long long h_bad = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, d_bad, sizeof(long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(LBM_E_HIP, "initial fields: %s", hipGetErrorString(e));
+    *n_bad = h_bad;
+    return LBM_OK;
+}
+
+// Fixed scratch of lbm_nn_fields_noalloc: every GPU the library runs on holds its own copy for the
+// life of the process.  Host code never uses the array's name as an address (on the host it is only
+// a stand-in): fields_scratch() looks up the device address once per device, with that device
+// current, and every later use goes through that address.
+constexpr int64_t kFieldsScratchSites = int64_t(1) << 18;  // 512 x 512 sites, 12.6 MB
+constexpr size_t kFieldsScratchWords = (6 * size_t(kFieldsScratchSites) * sizeof(double) + sizeof(long long) + 7) / 8;
+__device__ __align__(256) double scratch[kFieldsScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+lbm_status fields_scratch(void** out)
+{
+    int dev = 0;
+    LBM_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_E_INVAL, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_E_HIP, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 lbm_status lbm_conv2d_forward(const void* in, const void* w, const float* bias, void* out, float* out32, int32_t n,
@@ -1137,36 +1215,32 @@ lbm_status lbm_nn_fields(const float* pred, int32_t stride, const uint8_t* solid
                          int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale, double rho0,
                          double* rho, double* ux, double* uy, int64_t* n_bad, void* stream)
 {
-    if (!pred || !solid || !rho || !ux || !uy || !n_bad) return fail(LBM_E_INVAL, "null argument");
-    if (nx < 1 || ny < 1 || int64_t(nx) * ny > INT32_MAX / 8 || stride < 3 || smooth_iters < 0 ||
-        smooth_iters > 1000 || (periodic != 0 && periodic != 1))
-        return fail(LBM_E_INVAL, "arguments out of range");
-    if (!std::isfinite(u_scale) || !std::isfinite(rho_scale) || !std::isfinite(rho0))
-        return fail(LBM_E_INVAL, "non-finite scale");
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    const int n = nx * ny;
-    void* work = nullptr;  // two sets of three fp64 planes, then the count
-    LBM_HIP_TRY(hipMalloc(&work, sizeof(double) * 6 * size_t(n) + sizeof(long long)));
-    double* t0 = static_cast<double*>(work);
-    double* t1 = t0 + 3 * size_t(n);
-    long long* d_bad = reinterpret_cast<long long*>(t1 + 3 * size_t(n));
-    hipLaunchKernelGGL(lbm::nn::k_unpack, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, pred, stride, solid, n,
-                       t0);
-    for (int i = 0; i < smooth_iters; ++i) {
-        hipLaunchKernelGGL(lbm::nn::k_smooth, dim3(lbm::nn::blocks(size_t(n))), dim3(256), 0, st, t0, t1, solid, nx, ny,
-                           periodic);
-        std::swap(t0, t1);
-    }
-    hipLaunchKernelGGL(lbm::nn::k_fields, dim3(1), dim3(1024), 0, st, t0, solid, n, u_scale, rho_scale, rho0, rho, ux,
-                       uy, d_bad);
-    long long h_bad = 0;
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, d_bad, sizeof(long long), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    lbm_status st = fields_check(pred, stride, solid, nx, ny, smooth_iters, periodic, u_scale, rho_scale, rho0, rho,
+                                 ux, uy, n_bad);
+    if (st != LBM_OK) return st;
+    void* work = nullptr;
+    LBM_HIP_TRY(hipMalloc(&work, fields_work_bytes(int64_t(nx) * ny)));
+    st = fields_run(pred, stride, solid, nx, ny, smooth_iters, periodic, u_scale, rho_scale, rho0, rho, ux, uy, n_bad,
+                    work, static_cast<hipStream_t>(stream));
     ignore(hipFree(work));
-    if (e != hipSuccess) return fail(LBM_E_HIP, "lbm_nn_fields: %s", hipGetErrorString(e));
-    *n_bad = h_bad;
-    return LBM_OK;
+    return st;
+}
+
+lbm_status lbm_nn_fields_noalloc(const float* pred, int32_t stride, const uint8_t* solid, int32_t nx, int32_t ny,
+                                 int32_t smooth_iters, int32_t periodic, double u_scale, double rho_scale,
+                                 double rho0, double* rho, double* ux, double* uy, int64_t* n_bad, void* stream)
+{
+    lbm_status st = fields_check(pred, stride, solid, nx, ny, smooth_iters, periodic, u_scale, rho_scale, rho0, rho,
+                                 ux, uy, n_bad);
+    if (st != LBM_OK) return st;
+    if (int64_t(nx) * ny > kFieldsScratchSites)
+        return fail(LBM_E_INVAL, "lbm_nn_fields_noalloc: %d x %d sites exceed its fixed scratch of %lld sites", nx,
+                    ny, (long long)kFieldsScratchSites);
+    void* work = nullptr;
+    st = fields_scratch(&work);
+    if (st != LBM_OK) return st;
+    return fields_run(pred, stride, solid, nx, ny, smooth_iters, periodic, u_scale, rho_scale, rho0, rho, ux, uy,
+                      n_bad, work, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -124,6 +124,9 @@ SIGNATURES = {
                                     _VP, C.c_int32, _VP]),
     "lbm_nn_fields": (C.c_int32, [_VP, C.c_int32, _VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                   C.c_double, C.c_double, _VP, _VP, _VP, C.POINTER(C.c_int64), _VP]),
+    "lbm_nn_fields_noalloc": (C.c_int32, [_VP, C.c_int32, _VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_double, C.c_double, C.c_double, _VP, _VP, _VP, C.POINTER(C.c_int64),
+                                          _VP]),
 }
 
 _lib = None
@@ -509,16 +512,18 @@ def nn_features(solid, links, nx, ny, kn_feature, ax_feature, ay_feature, out, s
 
 
 def nn_fields(pred, solid, nx, ny, u_scale, rho_scale, rho0, rho, ux, uy, smooth_iters=0, periodic=False,
-              stream=None):
-    """lbm_nn_fields; returns the number of fluid sites with a non-finite prediction."""
+              stream=None, noalloc=False):
+    """lbm_nn_fields (or lbm_nn_fields_noalloc, which uses the library's fixed scratch instead of
+    allocating); returns the number of fluid sites with a non-finite prediction."""
     import torch
     assert pred.dtype == torch.float32 and pred.numel() == nx * ny * pred.shape[-1] and pred.shape[-1] >= 3
     assert solid.numel() == nx * ny and solid.dtype == torch.uint8
     assert all(t.numel() == nx * ny and t.dtype == torch.float64 for t in (rho, ux, uy))
     bad = C.c_int64()
-    _check(load().lbm_nn_fields(_ptr(pred), pred.shape[-1], _ptr(solid), nx, ny, int(smooth_iters), int(bool(periodic)),
-                                float(u_scale), float(rho_scale), float(rho0), _ptr(rho), _ptr(ux), _ptr(uy),
-                                C.byref(bad), _stream_handle(stream)))
+    fn = load().lbm_nn_fields_noalloc if noalloc else load().lbm_nn_fields
+    _check(fn(_ptr(pred), pred.shape[-1], _ptr(solid), nx, ny, int(smooth_iters), int(bool(periodic)),
+              float(u_scale), float(rho_scale), float(rho0), _ptr(rho), _ptr(ux), _ptr(uy), C.byref(bad),
+              _stream_handle(stream)))
     return int(bad.value)
 
 
