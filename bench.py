@@ -6,7 +6,10 @@ body acceleration 1e-6, rest start, the paper's prescription for l, r and tau_q.
 
 One timed step is one pass of the hot path: the fused collide-stream-boundary kernel over the whole
 lattice, with the convergence monitor (residual and mass reductions) run every 100 steps as a
-steady-state solve would.  Inputs are resident in HBM before the timed region.  The headline value
+steady-state solve would (and at the end of every shorter timed block).  Inputs are resident in HBM
+before the timed region.  Both precisions' lattices are set up before either is timed; the FP64 leg
+is timed first, so that the FP32 headline is not timed while the GPU's clocks come back up from the
+idle set-up period (about the first 100 steps).  The headline value
 is FP32-shifted storage (fp32 deviations, fp32 collision); the FP64 storage figure is reported
 beside it.  MLUPS counts lattice sites (solid included); MFLUPS counts fluid nodes.
 
@@ -33,13 +36,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_precision(problem, precision, steps, warmup, block, repeats=4):
+def time_precision(lat, steps, warmup, repeats=4):
+    """W warm-up steps, then the timed block of exactly `steps` steps (its figures are the ones
+    reported), then `repeats` more blocks that only show the spread."""
     import statistics
     import torch
-    from paper_2012_14707_amd import lbm
 
-    lat = lbm.Lattice(problem, precision=precision)
-    lat.set_launch(block)
     info = lat.info
     lat.step(warmup)
     lat.residual()
@@ -87,7 +89,6 @@ def time_precision(problem, precision, steps, warmup, block, repeats=4):
         repeats={"blocks": len(spread), "median_ms_per_step": round(statistics.median(spread), 5),
                  "min_ms_per_step": round(min(spread), 5), "max_ms_per_step": round(max(spread), 5)},
     )
-    lat.close()
     return out
 
 
@@ -105,9 +106,11 @@ def counted_traffic(precision, n):
     data = json.loads(m.group(1))
     if data.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
+    # counted bytes over the kernel duration of the same profiling run: both figures come from one box
+    gbs = (data["read_bytes"] + data["write_bytes"]) / (data["avg_duration_ns"] * 1e-9) / 1e9
     return dict(read_bytes=data["read_bytes"], write_bytes=data["write_bytes"],
                 steps_per_dispatch=data.get("steps_per_dispatch", 1),
-                profiled_avg_ns=data["avg_duration_ns"], source=os.path.relpath(path, ROOT))
+                profiled_avg_ns=data["avg_duration_ns"], traffic_gbs=gbs, source=os.path.relpath(path, ROOT))
 
 
 def batched_sweep(steps=2000, solve_cap=100_000, tol=1e-8):
@@ -154,29 +157,19 @@ def batched_sweep(steps=2000, solve_cap=100_000, tol=1e-8):
     log(f"[bench] sequential: {t_seq:.3f} s ({sites * steps / t_seq / 1e6:.0f} MLUPS)")
     b.init_rest()
     t0 = time.perf_counter()
-    status, nsteps, res = b.solve(tol, check_every=CHECK_EVERY, max_steps=solve_cap)
+    status, nsteps, res, fell = b.solve_fallback(tol, check_every=CHECK_EVERY, max_steps=solve_cap)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
     updates = sum(int(p["solid"].size) * int(n) for p, n in zip(pbs, nsteps))
     counts = {k: status.count(k) for k in sorted(set(status))}
-    log(f"[bench] batched solve to {tol:g}: {t_solve:.2f} s, {counts}, {updates / t_solve / 1e6:.0f} MLUPS aggregate")
+    # instances that went non-finite under the paper's l rule were re-run by the library with every
+    # negative l clamped to zero (lbm_batch_solve_fallback); their statuses are the re-run's
+    fallback = {str(i): {"status": status[i], "steps": int(nsteps[i]), "residual": float(res[i])}
+                for i in range(len(pbs)) if fell[i]}
+    log(f"[bench] batched solve to {tol:g} with the clamp fallback: {t_solve:.2f} s, {counts}, "
+        f"{updates / t_solve / 1e6:.0f} MLUPS aggregate; re-run with l clamped at 0: {fallback}")
     b.close()
-    # instances that went non-finite under the paper's l rule are re-run with every negative l
-    # clamped to zero (the stability fallback)
-    diverged = [i for i, st in enumerate(status) if st == "diverged"]
-    fallback = {}
-    if diverged:
-        again = []
-        for i in diverged:
-            pb = dict(pbs[i])
-            pb["params"] = dict(pbs[i]["params"], l_mode="clamp_neg")
-            again.append(pb)
-        rb = lbm.Batch(again, precision="fp32")
-        st2, n2, r2 = rb.solve(tol, check_every=CHECK_EVERY, max_steps=solve_cap)
-        rb.close()
-        fallback = {str(i): {"status": s2, "steps": int(k2), "residual": float(x2)}
-                    for i, s2, k2, x2 in zip(diverged, st2, n2, r2)}
-        log(f"[bench] fallback (l clamped at 0) for diverged instances: {fallback}")
+    diverged = [int(i) for i in fallback]
     return {
         "workload": "256 instances: 128 slip Poiseuille (rows U{16..512}, 4 columns, gamma U[0.05,0.95]) and "
                     "128 Couette annuli (R2 U[16,128], ratio 0.5), Kn log-U[1e-3,0.1], FP32-shifted, seed 1",
@@ -223,21 +216,32 @@ def warm_start(n_eval=40, tol=1e-8):
     return {k: (round(v, 4) if isinstance(v, float) and k != "tol" else v) for k, v in out.items()}
 
 
-def copy_bandwidth(mib=1024, reps=10):
-    """Read + write GB/s of a plain device-to-device copy (the practical streaming ceiling that the
-    step kernel's counted traffic is compared with), timed with HIP events."""
+def copy_bandwidth(mib=1024, reps=20, min_ms=0.0):
+    """Read + write GB/s of the library's streaming copy (lbm_stream_copy, 16-byte words) of `mib`
+    MiB, timed with HIP events over the last `reps` copies of a run that streams for at least
+    `min_ms` milliseconds: the practical streaming ceiling that the step kernel's counted HBM
+    traffic is compared with."""
     import torch
+    from paper_2012_14707_amd import lbm
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(10):
+            lbm.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        if (time.perf_counter() - t0) * 1e3 >= min_ms:
+            break
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        lbm.stream_copy(dst, src)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    assert bool(torch.equal(dst, src))
     del src, dst
     return 8.0 * n / (ms * 1e-3) / 1e9
 
@@ -250,14 +254,43 @@ from paper_2012_14707_amd import geometry as G
 pb = G.throughput_config3(n={n}, seed=0)
 o = oracle.Oracle(pb["params"], pb["solid"], pb["links"])
 t = time.perf_counter()
-o.step(1)
-print(pb["solid"].size / (time.perf_counter() - t) / 1e6)
+o.step({steps})
+print(pb["solid"].size * {steps} / (time.perf_counter() - t) / 1e6)
 """
 
 
-def cpu_baseline(problem, steps=2, single_thread=True):
-    """The oracle as it stands on this host's cores: `steps` steps of the full lattice; and one step
-    with a single OpenMP thread, in a child process (the thread count is read at library load)."""
+def time_to_steady(tol=1e-10, check_every=CHECK_EVERY):
+    """Configurations 1 and 2 run from rest to residual <= tol in FP64, by the oracle on the host's
+    cores and by the library on the GPU (residual checked every check_every steps on both)."""
+    import oracle
+    from paper_2012_14707_amd import geometry as G
+    from paper_2012_14707_amd import lbm
+    cases = [("slip Poiseuille 4x22, Kn 0.1", G.poiseuille_config1())]
+    cases += [(f"Couette 132^2, Kn {kn}", G.couette_config2(kn)) for kn in (0.1, 0.05, 0.01)]
+    rows = []
+    for name, pb in cases:
+        ora = oracle.Oracle(pb["params"], pb["solid"], pb["links"])
+        t0 = time.perf_counter()
+        s_o, r_o = ora.run_to_steady(tol, check_every)
+        t_o = time.perf_counter() - t0
+        lat = lbm.Lattice(pb, precision="fp64")
+        lat.step(2)
+        lat.residual()
+        lat.init_rest()
+        t0 = time.perf_counter()
+        s_g, r_g = lat.run_to_steady(tol, check_every)
+        t_g = time.perf_counter() - t0
+        lat.close()
+        rows.append({"case": name, "oracle_steps": int(s_o), "oracle_s": round(t_o, 3), "gpu_steps": int(s_g),
+                     "gpu_s": round(t_g, 4), "speedup": round(t_o / t_g, 1)})
+        log(f"[bench] to residual {tol:g}: {name}: oracle {s_o} steps {t_o:.2f} s, GPU {s_g} steps {t_g:.3f} s")
+    return rows
+
+
+def cpu_baseline(problem, steps=20, single_steps=1):
+    """The oracle as it stands on this host's cores: `steps` steps of the full lattice on every core;
+    `single_steps` steps with one OpenMP thread, in a child process (the thread count is read at
+    library load); and configurations 1 and 2 to steady state beside the GPU's time."""
     import subprocess
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
@@ -267,18 +300,28 @@ def cpu_baseline(problem, steps=2, single_thread=True):
     ora.step(steps)
     t2 = time.perf_counter()
     n_sites = problem["solid"].size
+    n_fluid = int((problem["solid"] == 0).sum())
     del ora
     out = dict(value=n_sites * steps / (t2 - t1) / 1e6, unit="MLUPS", cores=threads, kind="oracle",
                sample=f"{steps} full steps of the {problem['solid'].shape[1]}x{problem['solid'].shape[0]} lattice "
                       "(x87 extended precision, OpenMP over sites); "
-                      f"setup {t1 - t0:.1f} s excluded")
-    if single_thread:
-        code = _SINGLE_THREAD.format(root=ROOT, n=problem["solid"].shape[0])
+                      f"setup {t1 - t0:.1f} s excluded",
+               mflups=n_fluid * steps / (t2 - t1) / 1e6)
+    try:
+        import platform
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")),
+                     platform.processor())
+        out["cpu_model"] = model
+    except OSError:
+        pass
+    if single_steps:
+        code = _SINGLE_THREAD.format(root=ROOT, n=problem["solid"].shape[0], steps=single_steps)
         env = dict(os.environ, OMP_NUM_THREADS="1")
-        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
         if r.returncode == 0:
             out["single_thread"] = {"value": float(r.stdout.strip().splitlines()[-1]), "unit": "MLUPS",
-                                    "sample": "1 full step of the same lattice, one OpenMP thread"}
+                                    "sample": f"{single_steps} full step(s) of the same lattice, one OpenMP thread"}
+    out["time_to_steady"] = time_to_steady()
     return out
 
 
@@ -307,13 +350,14 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
+        from paper_2012_14707_amd import lbm
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(20):
-            dst.copy_(src)
+            lbm.stream_copy(dst, src)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / 20
         print(json.dumps({"copy_mib": args.copy_calibration, "read_bytes": 4 * n, "write_bytes": 4 * n,
@@ -332,10 +376,22 @@ def main():
     pb = G.throughput_config3(n=args.n, seed=0)
     log(f"[bench] geometry {time.perf_counter() - t0:.1f} s: {G.counts(pb)} (fluid, sites, links)")
 
+    # Both lattices are set up (host work, about a second each, with the GPU idle) before either is
+    # timed.  After such an idle period the GPU needs about 100 steps (some 30 ms of load) to come
+    # back to its sustained clocks, so the leg timed first reads up to 8% slow in a window of tens
+    # of steps while the one timed second does not.  The FP64 leg goes first and the FP32 headline
+    # second; FP64's timed_blocks show its ramp.
+    from paper_2012_14707_amd import lbm
+    order = [args.only] if args.only else ["fp64", "fp32"]
+    lats = {}
+    for precision in order:
+        lats[precision] = lbm.Lattice(pb, precision=precision)
+        lats[precision].set_launch(args.block)
     results = {}
-    for precision in ([args.only] if args.only else ["fp32", "fp64"]):
+    for precision in order:
         log(f"[bench] {precision}: warmup {args.warmup}, timing {args.steps} steps")
-        results[precision] = time_precision(pb, precision, args.steps, args.warmup, args.block)
+        results[precision] = time_precision(lats[precision], args.steps, args.warmup)
+        lats.pop(precision).close()
         r = results[precision]
         log(f"[bench] {precision}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, kernel "
             f"{r['kernel_avg_ms']:.4f} ms, {r['achieved_gbs']:.0f} GB/s algorithmic")
@@ -380,16 +436,16 @@ def main():
         "mflups": round(head["mflups"], 1),
     }
     cb = copy_bandwidth()
-    line["copy_bandwidth"] = {"gbs": round(cb, 1), "workload": "1 GiB device copy, read + write bytes",
+    line["copy_bandwidth"] = {"gbs": round(cb, 1), "workload": "1 GiB lbm_stream_copy, read + write bytes",
                               "achieved_over_copy": round(head["achieved_gbs"] / cb, 4)}
     counted = counted_traffic(head_name, args.n)
     if counted and counted["steps_per_dispatch"] == head["steps_per_launch"]:
-        total = counted["read_bytes"] + counted["write_bytes"]
-        per_launch_ms = head["kernel_avg_ms"] * counted["steps_per_dispatch"]
-        line["roofline"]["traffic"] = round(total / (per_launch_ms * 1e-3) / 1e9, 1)
+        line["roofline"]["traffic"] = round(counted["traffic_gbs"], 1)
         line["hbm_counters"] = {"read_bytes": round(counted["read_bytes"]), "write_bytes": round(counted["write_bytes"]),
-                                "steps_per_dispatch": counted["steps_per_dispatch"], "source": counted["source"]}
-        line["copy_bandwidth"]["traffic_over_copy"] = round(line["roofline"]["traffic"] / cb, 4)
+                                "steps_per_dispatch": counted["steps_per_dispatch"],
+                                "profiled_avg_us_per_dispatch": round(counted["profiled_avg_ns"] / 1e3, 2),
+                                "traffic_gbs": "counted bytes per dispatch / profiled duration, both from the "
+                                               "profiling run", "source": counted["source"]}
     if "fp64" in results and head_name != "fp64":
         r = results["fp64"]
         line["fp64"] = {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
@@ -400,11 +456,12 @@ def main():
                         "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "timed_blocks": r["repeats"]}
         c64 = counted_traffic("fp64", args.n)
         if c64 and c64["steps_per_dispatch"] == r["steps_per_launch"]:
-            per_launch_ms = r["kernel_avg_ms"] * c64["steps_per_dispatch"]
-            line["fp64"]["traffic"] = round((c64["read_bytes"] + c64["write_bytes"]) / (per_launch_ms * 1e-3) / 1e9, 1)
+            line["fp64"]["traffic"] = round(c64["traffic_gbs"], 1)
             line["fp64"]["hbm_counters"] = {"read_bytes": round(c64["read_bytes"]),
                                             "write_bytes": round(c64["write_bytes"]),
-                                            "steps_per_dispatch": c64["steps_per_dispatch"], "source": c64["source"]}
+                                            "steps_per_dispatch": c64["steps_per_dispatch"],
+                                            "profiled_avg_us_per_dispatch": round(c64["profiled_avg_ns"] / 1e3, 2),
+                                            "source": c64["source"]}
     if not args.no_batched and not args.only:
         log("[bench] batched sweep (256 uneven instances)")
         line["batched"] = batched_sweep()
@@ -415,7 +472,8 @@ def main():
         log(f"[bench] warm start: step ratio median {w['step_ratio_median']}, wall ratio median "
             f"{w['wall_ratio_median']}, forward {w['nn_forward_tflops']} TFLOP/s")
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline: oracle, 2 steps of the full lattice on the host cores")
+        log("[bench] cpu baseline: oracle, 20 steps of the full lattice on the host cores, 1 on one thread, "
+            "configurations 1 and 2 to steady state")
         line["cpu_baseline"] = cpu_baseline(pb)
         log(f"[bench] cpu baseline {line['cpu_baseline']['value']:.2f} MLUPS on {line['cpu_baseline']['cores']} threads")
     print(json.dumps(line), flush=True)
