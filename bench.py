@@ -216,6 +216,46 @@ def warm_start(n_eval=40, tol=1e-8):
     return {k: (round(v, 4) if isinstance(v, float) and k != "tol" else v) for k, v in out.items()}
 
 
+def nn_throughput(batch=8, reps=10):
+    """The warm-start network on the matrix cores at batch `batch` (256^2, 5 levels, 32 base channels,
+    periodic convolutions): forward passes and whole training steps (forward, loss and every
+    gradient, Adam), timed with HIP events on the network's stream over `reps` repetitions."""
+    import torch
+    from paper_2012_14707_amd import lbm
+    from paper_2012_14707_amd import warmstart as W
+    net = lbm.Net(max_batch=batch, seed=1, **W.NET_SHAPE)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn((batch, W.SIDE, W.SIDE, net.in_pad), device="cuda", generator=g).to(torch.bfloat16)
+    target = torch.randn((batch, W.SIDE, W.SIDE, W.OUT_CHANNELS), device="cuda", generator=g)
+    mask = (torch.rand((batch, W.SIDE, W.SIDE), device="cuda", generator=g) < 0.7).to(torch.uint8)
+    for _ in range(3):
+        net.forward(x)
+        net.backward(target, mask)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        net.forward(x)
+    e[1].record()
+    e[2].record()
+    for _ in range(reps):
+        net.forward(x)
+        net.backward(target, mask)
+        net.adam_step(1e-4)
+    e[3].record()
+    torch.cuda.synchronize()
+    fwd_ms = e[0].elapsed_time(e[1]) / reps
+    step_ms = e[2].elapsed_time(e[3]) / reps
+    flops = W.forward_flops(batch=batch)
+    net.close()
+    return {"batch": batch, "forward_ms": round(fwd_ms, 4), "forward_tflops": round(flops / fwd_ms / 1e9, 1),
+            "forward_frac_bf16_peak": round(flops / fwd_ms / 1e9 / 2500.0, 4),
+            "train_step_ms": round(step_ms, 4),
+            # a training step is one forward and two backward products (input and weight gradients)
+            "train_step_tflops": round(3 * flops / step_ms / 1e9, 1)}
+
+
 def copy_bandwidth(mib=1024, reps=20, min_ms=0.0):
     """Read + write GB/s of the library's streaming copy (lbm_stream_copy, 16-byte words) of `mib`
     MiB, timed with HIP events over the last `reps` copies of a run that streams for at least
@@ -333,7 +373,7 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "warm", "batched"], default=None,
+    ap.add_argument("--only", choices=["fp32", "fp64", "warm", "batched", "nn"], default=None,
                     help="one storage precision of the throughput step, or only the warm-start or batched leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sweep measurement")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start measurement")
@@ -366,6 +406,10 @@ def main():
     if args.only == "warm":
         log("[bench] learned warm start vs rest only")
         print(json.dumps({"metric": METRIC, "warm_start": warm_start()}), flush=True)
+        return
+    if args.only == "nn":
+        log("[bench] warm-start network throughput only")
+        print(json.dumps({"metric": METRIC, "nn": nn_throughput()}), flush=True)
         return
     if args.only == "batched":
         log("[bench] batched sweep only")
@@ -471,6 +515,8 @@ def main():
         w = line["warm_start"]
         log(f"[bench] warm start: step ratio median {w['step_ratio_median']}, wall ratio median "
             f"{w['wall_ratio_median']}, forward {w['nn_forward_tflops']} TFLOP/s")
+        line["nn"] = nn_throughput()
+        log(f"[bench] network at batch 8: {line['nn']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle, 20 steps of the full lattice on the host cores, 1 on one thread, "
             "configurations 1 and 2 to steady state")

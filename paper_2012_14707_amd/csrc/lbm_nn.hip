@@ -56,6 +56,8 @@ struct ConvArgs {
     float* yf;          // fp32 output [pixels][Cout] (null: none)
     int N, H, W, Cin, Cout, relu;
     int periodic;       // 1: rows and columns wrap around; 0: zero padding
+    float* part;        // split K: fp32 partial sums [splits][pixels][Cout] (null: no split)
+    int kper;           // split K: K range of one split (a multiple of TK)
 };
 
 __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, int& x)
@@ -69,7 +71,7 @@ __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, i
 // out[p][co] = act(bias[co] + sum_{tap, ci} x[p + off(tap)][ci] w[tap][co][ci]), with zero padding
 // or periodic wrap-around at the image edges.
 // One block of four waves computes a BM-pixel x BN-channel tile (the launcher picks the largest of
-// 256 x 32, 128 x 64, 64 x 64, 64 x 32 that still gives enough blocks to fill the chip); the waves
+// 128 x 64, 128 x 32, 64 x 64, 64 x 32 that still gives enough blocks to fill the chip); the waves
 // form a WGM x WGN grid and each multiplies a (BM / WGM) x (BN / WGN) part with 16x16x32 MFMAs.  K runs over (tap, ci);
 // Cin is a multiple of 8 so every 8-wide K group lies in one tap and is one 16-byte load.  The
 // next K step's operands are loaded into registers while the current one is multiplied, and LDS
@@ -86,7 +88,9 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int P = a.N * a.H * a.W;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int K = TAPS * a.Cin;
+    // this block's K range: the whole of it, or split blockIdx.z of a split-K launch
+    const int kb = a.part ? blockIdx.z * a.kper : 0;
+    const int K = a.part ? min(TAPS * a.Cin, kb + a.kper) : TAPS * a.Cin;
     const int lg = tid % 4;  // 8-wide K group loaded by this thread
     int pn[AR], py[AR], px[AR];
     bool pin[AR];
@@ -138,11 +142,11 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
         for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     const int wm = (wave / WGN) * (BM / WGM), wn = (wave % WGN) * (BN / WGN);
 
-    load(0);
+    load(kb);
     stash(0);
     __syncthreads();
     int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += TK) {
+    for (int k0 = kb; k0 < K; k0 += TK) {
         const bool more = k0 + TK < K;
         if (more) load(k0 + TK);
         // A operand: lane holds row lane % 16, k = 8 (lane / 16) .. +7; B likewise by column
@@ -163,6 +167,21 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
         buf ^= 1;
     }
     // result: lane holds column lane % 16, rows 4 (lane / 16) + r
+    if (a.part) {  // split K: raw partial sums; k_split_sum adds the splits, the bias and the activation
+        float* out = a.part + size_t(blockIdx.z) * P * a.Cout;
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int col = n0 + wn + 16 * j + lane % 16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm + 16 * i + 4 * (lane / 16) + r;
+                    if (row < P && col < a.Cout) out[size_t(row) * a.Cout + col] = acc[i][j][r];
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -180,6 +199,24 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
                 if (a.yf) a.yf[size_t(row) * a.Cout + col] = v;
             }
         }
+}
+
+// Epilogue of a split-K convolution: out[p][co] = act(bias[co] + sum over splits s, in order, of
+// part[s][p][co]).
+__global__ void __launch_bounds__(256) k_split_sum(const ConvArgs a, int splits)
+{
+    const size_t P = size_t(a.N) * a.H * a.W;
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= P * a.Cout) return;
+    const int col = int(e % a.Cout);
+    const size_t row = e / a.Cout;
+    float v = a.bias ? a.bias[col] : 0.f;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += a.part[size_t(k) * P * a.Cout + e];
+    v += s;
+    if (a.relu) v = fmaxf(v, 0.f);
+    if (a.y.p) a.y.p[row * a.y.cs + a.y.co + col] = bf16(v);
+    if (a.yf) a.yf[e] = v;
 }
 
 struct WgradArgs {
@@ -271,15 +308,35 @@ __global__ void __launch_bounds__(256) k_sum_splits(const float* partial, int ns
     grad[e] = s;
 }
 
-// Bias gradient partials: part[b][co] = sum of dz[p][co] over pixel block b (256 pixels).
-__global__ void __launch_bounds__(256) k_bias_partial(CSlice dz, int P, int Cout, float* part)
+// Bias gradient partials: part[b][co] = sum of dz[p][co] over the pixels p of chunk b (chunk pixels
+// each).  Eight channels per thread; the block's threads split the chunk into L = 256 / (Cout / 8)
+// interleaved pixel lanes (one lane per thread when Cout > 2048), summed in a fixed order.
+__global__ void __launch_bounds__(256) k_bias_partial(CSlice dz, int P, int Cout, int chunk, float* part)
 {
-    const int pb = blockIdx.x;
-    const int p1 = min(P, (pb + 1) * 256);
-    for (int co = threadIdx.x; co < Cout; co += 256) {
-        float s = 0.f;
-        for (int p = pb * 256; p < p1; ++p) s += float(dz.p[size_t(p) * dz.cs + dz.co + co]);
-        part[size_t(pb) * Cout + co] = s;
+    __shared__ float sh[256 * 8];
+    const int G = Cout / 8;
+    const int L = G >= 256 ? 1 : 256 / G;
+    const int p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+    for (int g0 = 0; g0 < G; g0 += 256) {
+        const int t = threadIdx.x, g = g0 + t % min(G, 256), lane = t / min(G, 256);
+        float acc[8] = {};
+        if (lane < L && g < G)
+            for (int p = p0 + lane; p < p1; p += L) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8*>(dz.p + size_t(p) * dz.cs + dz.co + 8 * g);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc[k] += float(v[k]);
+            }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sh[t * 8 + k] = acc[k];
+        __syncthreads();
+        const int gs = min(G - g0, 256);
+        for (int c = threadIdx.x; c < gs * 8; c += 256) {
+            // channel c of this pass: group c / 8, lane sums in order
+            float s = 0.f;
+            for (int l = 0; l < L; ++l) s += sh[(l * min(G, 256) + c / 8) * 8 + c % 8];
+            part[size_t(blockIdx.x) * Cout + 8 * g0 + c] = s;
+        }
+        __syncthreads();
     }
 }
 
@@ -307,70 +364,98 @@ __global__ void __launch_bounds__(256) k_flip(const T* w, bf16* wt, int taps, in
 
 // ------------------------------------------------------------------------ elementwise kernels
 
+// The elementwise kernels below move eight channels (one 16-byte bf16x8) per thread: channel counts,
+// slice offsets and strides are multiples of 8, so every group is one aligned vector access.
+__device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+__device__ __forceinline__ void st8(bf16* p, bf16x8 v) { *reinterpret_cast<bf16x8*>(p) = v; }
+
 // dz[p][c] = g[p][c] if y[p][c] > 0 else 0 (ReLU backward; dz contiguous with C channels)
 __global__ void __launch_bounds__(256) k_relu_bwd(CSlice g, CSlice y, bf16* dz, int P, int C)
 {
+    const int G = C / 8;
     const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= size_t(P) * C) return;
-    const size_t p = e / C, c = e - p * C;
-    const float yv = float(y.p[p * y.cs + y.co + c]);
-    dz[e] = yv > 0.f ? g.p[p * g.cs + g.co + c] : bf16(0.f);
+    if (e >= size_t(P) * G) return;
+    const size_t p = e / G;
+    const int c = int(e - p * G) * 8;
+    const bf16x8 yv = ld8(y.p + p * y.cs + y.co + c), gv = ld8(g.p + p * g.cs + g.co + c);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = float(yv[k]) > 0.f ? gv[k] : bf16(0.f);
+    st8(dz + p * C + c, o);
 }
 
 // 2x2 average pooling: out (H/2 x W/2) from in (H x W)
 __global__ void __launch_bounds__(256) k_pool_fwd(CSlice in, Slice out, int N, int H, int W, int C)
 {
-    const int Ho = H / 2, Wo = W / 2;
+    const int Ho = H / 2, Wo = W / 2, G = C / 8;
     const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= size_t(N) * Ho * Wo * C) return;
-    const int c = int(e % C);
-    const size_t q = e / C;
+    if (e >= size_t(N) * Ho * Wo * G) return;
+    const int c = int(e % G) * 8;
+    const size_t q = e / G;
     const int x = int(q % Wo), y = int((q / Wo) % Ho), n = int(q / (size_t(Wo) * Ho));
-    float s = 0.f;
+    float s[8] = {};
     for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx)
-            s += float(in.p[size_t((n * H + 2 * y + dy) * W + 2 * x + dx) * in.cs + in.co + c]);
-    out.p[q * out.cs + out.co + c] = bf16(0.25f * s);
+        for (int dx = 0; dx < 2; ++dx) {
+            const bf16x8 v = ld8(in.p + size_t((n * H + 2 * y + dy) * W + 2 * x + dx) * in.cs + in.co + c);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += float(v[k]);
+        }
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = bf16(0.25f * s[k]);
+    st8(out.p + q * out.cs + out.co + c, o);
 }
 
 // gin[2y+dy][2x+dx][c] += gout[y][x][c] / 4   (gin at H x W)
 __global__ void __launch_bounds__(256) k_pool_bwd_add(CSlice gout, Slice gin, int N, int H, int W, int C)
 {
+    const int G = C / 8;
     const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= size_t(N) * H * W * C) return;
-    const int c = int(e % C);
-    const size_t q = e / C;
+    if (e >= size_t(N) * H * W * G) return;
+    const int c = int(e % G) * 8;
+    const size_t q = e / G;
     const int x = int(q % W), y = int((q / W) % H), n = int(q / (size_t(W) * H));
-    const float g = 0.25f * float(gout.p[size_t((n * (H / 2) + y / 2) * (W / 2) + x / 2) * gout.cs + gout.co + c]);
-    bf16& t = gin.p[q * gin.cs + gin.co + c];
-    t = bf16(float(t) + g);
+    const bf16x8 gv = ld8(gout.p + size_t((n * (H / 2) + y / 2) * (W / 2) + x / 2) * gout.cs + gout.co + c);
+    bf16* t = gin.p + q * gin.cs + gin.co + c;
+    const bf16x8 tv = ld8(t);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = bf16(float(tv[k]) + 0.25f * float(gv[k]));
+    st8(t, o);
 }
 
 // nearest 2x upsampling: out (2H x 2W) from in (H x W)
 __global__ void __launch_bounds__(256) k_up_fwd(CSlice in, Slice out, int N, int H, int W, int C)
 {
+    const int H2 = 2 * H, W2 = 2 * W, G = C / 8;
     const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-    const int H2 = 2 * H, W2 = 2 * W;
-    if (e >= size_t(N) * H2 * W2 * C) return;
-    const int c = int(e % C);
-    const size_t q = e / C;
+    if (e >= size_t(N) * H2 * W2 * G) return;
+    const int c = int(e % G) * 8;
+    const size_t q = e / G;
     const int x = int(q % W2), y = int((q / W2) % H2), n = int(q / (size_t(W2) * H2));
-    out.p[q * out.cs + out.co + c] = in.p[size_t((n * H + y / 2) * W + x / 2) * in.cs + in.co + c];
+    st8(out.p + q * out.cs + out.co + c, ld8(in.p + size_t((n * H + y / 2) * W + x / 2) * in.cs + in.co + c));
 }
 
 // gin[y][x][c] = sum of the four gout values it was copied to (gin at H x W)
 __global__ void __launch_bounds__(256) k_up_bwd(CSlice gout, Slice gin, int N, int H, int W, int C)
 {
+    const int G = C / 8;
     const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= size_t(N) * H * W * C) return;
-    const int c = int(e % C);
-    const size_t q = e / C;
+    if (e >= size_t(N) * H * W * G) return;
+    const int c = int(e % G) * 8;
+    const size_t q = e / G;
     const int x = int(q % W), y = int((q / W) % H), n = int(q / (size_t(W) * H));
-    float s = 0.f;
+    float s[8] = {};
     for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx)
-            s += float(gout.p[size_t((n * 2 * H + 2 * y + dy) * 2 * W + 2 * x + dx) * gout.cs + gout.co + c]);
-    gin.p[q * gin.cs + gin.co + c] = bf16(s);
+        for (int dx = 0; dx < 2; ++dx) {
+            const bf16x8 v = ld8(gout.p + size_t((n * 2 * H + 2 * y + dy) * 2 * W + 2 * x + dx) * gout.cs + gout.co + c);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += float(v[k]);
+        }
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = bf16(s[k]);
+    st8(gin.p + q * gin.cs + gin.co + c, o);
 }
 
 // Fluid pixel count of the mask, per 256-pixel block.
@@ -576,11 +661,44 @@ inline unsigned blocks(size_t n) { return unsigned((n + 255) / 256); }
 
 // ------------------------------------------------------------------------------- launchers
 
-hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
-                        int Cout, int taps, bool relu, bool periodic, hipStream_t st)
+// Splits of the K range for a convolution whose 64 x 64 grid has too few blocks to fill the chip:
+// enough splits for about 1024 blocks, at most 8, each at least 16 K steps long (1 = no split).
+int fwd_splits(long P, int Cin, int Cout, int taps)
 {
-    ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0};
+    const long tiles = ((P + 63) / 64) * ((Cout + 63) / 64);
+    if (Cout < 64 || tiles >= 1024) return 1;
+    const int K = taps * Cin;
+    int s = int(std::min<long>(8, 1024 / std::max<long>(tiles, 1)));
+    while (s > 1 && K / s < 16 * TK) --s;
+    return std::max(1, s);
+}
+
+size_t fwd_split_elems(long P, int Cin, int Cout, int taps)
+{
+    const int s = fwd_splits(P, Cin, Cout, taps);
+    return s > 1 ? size_t(s) * size_t(P) * size_t(Cout) : 0;
+}
+
+hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
+                        int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems)
+{
+    ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0};
     const long P = long(N) * H * W;
+    // split K over a workspace when the grid alone cannot fill the chip
+    const int splits = fwd_splits(P, Cin, Cout, taps);
+    if (splits > 1 && ws && ws_elems >= fwd_split_elems(P, Cin, Cout, taps)) {
+        const int K = taps * Cin;
+        a.part = ws;
+        a.kper = ((K + splits - 1) / splits + TK - 1) / TK * TK;
+        const int nsplit = (K + a.kper - 1) / a.kper;
+        const dim3 grid(unsigned((P + 63) / 64), unsigned((Cout + 63) / 64), unsigned(nsplit));
+        if (taps == 9)
+            hipLaunchKernelGGL((k_conv_fwd<9, 64, 64>), grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_conv_fwd<1, 64, 64>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
+        return hipGetLastError();
+    }
     // the largest tile that still leaves about four blocks per compute unit (256 CUs)
     auto blocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
     auto go = [&](auto kern, int bm, int bn) {
@@ -592,8 +710,8 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         t9 ? go(k_conv_fwd<9, 128, 64>, 128, 64) : go(k_conv_fwd<1, 128, 64>, 128, 64);
     else if (Cout >= 64)
         t9 ? go(k_conv_fwd<9, 64, 64>, 64, 64) : go(k_conv_fwd<1, 64, 64>, 64, 64);
-    else if (blocks(256, 32) >= 1024)
-        t9 ? go(k_conv_fwd<9, 256, 32>, 256, 32) : go(k_conv_fwd<1, 256, 32>, 256, 32);
+    else if (blocks(128, 32) >= 1024)
+        t9 ? go(k_conv_fwd<9, 128, 32>, 128, 32) : go(k_conv_fwd<1, 128, 32>, 128, 32);
     else
         t9 ? go(k_conv_fwd<9, 64, 32>, 64, 32) : go(k_conv_fwd<1, 64, 32>, 64, 32);
     return hipGetLastError();
@@ -610,13 +728,13 @@ hipError_t flip(const T* w, bf16* wt, int taps, int Cout, int Cin, hipStream_t s
 // channel roles exchanged (the adjoint of a zero-padded or of a periodic convolution is the
 // convolution with the mirrored kernel under the same edge rule).
 hipError_t conv_dgrad(CSlice dz, const bf16* wt, Slice dx, int N, int H, int W, int Cin, int Cout, int taps,
-                      bool periodic, hipStream_t st)
+                      bool periodic, hipStream_t st, float* ws, size_t ws_elems)
 {
-    return conv_forward(dz, wt, nullptr, dx, nullptr, N, H, W, Cout, Cin, taps, false, periodic, st);
+    return conv_forward(dz, wt, nullptr, dx, nullptr, N, H, W, Cout, Cin, taps, false, periodic, st, ws, ws_elems);
 }
 
 struct WgradPlan {
-    int nsplit, chunk, nb;
+    int nsplit, chunk, nb, bchunk;
     size_t per, elems;
 };
 
@@ -629,7 +747,8 @@ WgradPlan wgrad_plan(int P, int Cin, int Cout, int taps)
     const int target = std::max(1, std::min(1024 / tiles, P / 256));
     w.chunk = ((P + target - 1) / target + TK - 1) / TK * TK;
     w.nsplit = std::max(1, (P + w.chunk - 1) / w.chunk);
-    w.nb = (P + 255) / 256;
+    w.nb = std::min(256, (P + 255) / 256);  // bias partials: at most 256 pixel chunks
+    w.bchunk = (P + w.nb - 1) / w.nb;
     w.per = size_t(taps) * Cout * Cin;
     w.elems = size_t(target) * w.per + size_t(w.nb) * Cout;
     return w;
@@ -649,7 +768,7 @@ hipError_t conv_wgrad(CSlice x, CSlice dz, float* dw, float* db, float* work, in
     hipLaunchKernelGGL(k_sum_splits, dim3(blocks(pl.per)), dim3(256), 0, st, work, pl.nsplit, pl.per, dw);
     if (db) {
         float* bpart = work + size_t(pl.nsplit) * pl.per;
-        hipLaunchKernelGGL(k_bias_partial, dim3(pl.nb), dim3(256), 0, st, dz, P, Cout, bpart);
+        hipLaunchKernelGGL(k_bias_partial, dim3(pl.nb), dim3(256), 0, st, dz, P, Cout, pl.bchunk, bpart);
         hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(size_t(Cout))), dim3(256), 0, st, bpart, pl.nb, Cout, db);
     }
     return hipGetLastError();
@@ -700,7 +819,8 @@ struct lbm_nn {
     bf16* wb = nullptr;                                            // bf16 copy of every parameter
     bf16* wt_all = nullptr;                                        // flipped bf16 kernels
     bf16* dz = nullptr;       // pre-activation gradient of the convolution being differentiated
-    float* work = nullptr;    // weight-gradient workspace
+    float* work = nullptr;    // weight-gradient and split-K workspace
+    size_t work_elems = 0;
     float* part = nullptr;    // loss / count partials
     float* yout = nullptr;    // last forward output, fp32 [P][kOutPad]
     bf16* g_out = nullptr;    // its gradient
@@ -743,7 +863,7 @@ Slice sl(bf16* p, int c, int off = 0) { return Slice{p, c, off}; }
 hipError_t fwd(lbm_nn* n, const Conv& c, CSlice x, Slice y, float* yf, int N, int H, int W, bool relu)
 {
     return lbm::nn::conv_forward(x, c.w, n->w + c.b_off, y, yf, N, H, W, c.cin, c.cout, c.taps, relu,
-                                 n->cfg.periodic != 0, n->stream);
+                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems);
 }
 
 hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, int W)
@@ -757,14 +877,15 @@ hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, in
 hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g, Slice gx, int N, int H, int W)
 {
     const int P = N * H * W;
-    hipLaunchKernelGGL(lbm::nn::k_relu_bwd, dim3(lbm::nn::blocks(size_t(P) * c.cout)), dim3(256), 0, n->stream, g, y,
+    hipLaunchKernelGGL(lbm::nn::k_relu_bwd, dim3(lbm::nn::blocks(size_t(P) * c.cout / 8)), dim3(256), 0, n->stream, g, y,
                        n->dz, P, c.cout);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const CSlice dz = cs(n->dz, c.cout);
     e = wgrad(n, c, x, dz, N, H, W);
     if (e != hipSuccess || !gx.p) return e;
-    return lbm::nn::conv_dgrad(dz, c.wt, gx, N, H, W, c.cin, c.cout, c.taps, n->cfg.periodic != 0, n->stream);
+    return lbm::nn::conv_dgrad(dz, c.wt, gx, N, H, W, c.cin, c.cout, c.taps, n->cfg.periodic != 0, n->stream,
+                               n->work, n->work_elems);
 }
 
 hipError_t refresh_flipped(lbm_nn* n)
@@ -873,7 +994,7 @@ lbm_status lbm_conv2d_forward(const void* in, const void* w, const float* bias, 
         return fail(LBM_E_INVAL, "bf16 tensors need 16-byte alignment");
     LBM_HIP_TRY(lbm::nn::conv_forward(cs(static_cast<const bf16*>(in), cin), static_cast<const bf16*>(w), bias,
                                       sl(static_cast<bf16*>(out), cout), out32, n, h, wd, cin, cout, ksize * ksize,
-                                      relu != 0, periodic != 0, static_cast<hipStream_t>(stream)));
+                                      relu != 0, periodic != 0, static_cast<hipStream_t>(stream), nullptr, 0));
     return LBM_OK;
 }
 
@@ -887,7 +1008,8 @@ lbm_status lbm_conv2d_dgrad(const void* dout, const void* w, void* din, void* wt
     const int taps = ksize * ksize;
     LBM_HIP_TRY(lbm::nn::flip(static_cast<const bf16*>(w), static_cast<bf16*>(wt), taps, cout, cin, st));
     LBM_HIP_TRY(lbm::nn::conv_dgrad(cs(static_cast<const bf16*>(dout), cout), static_cast<const bf16*>(wt),
-                                    sl(static_cast<bf16*>(din), cin), n, h, wd, cin, cout, taps, periodic != 0, st));
+                                    sl(static_cast<bf16*>(din), cin), n, h, wd, cin, cout, taps, periodic != 0, st,
+                                    nullptr, 0));
     return LBM_OK;
 }
 
@@ -987,7 +1109,11 @@ lbm_status lbm_nn_create(const lbm_nn_config* cfg, uint64_t seed, void* stream, 
     for (const Conv* cv : n->convs) {
         const int P = int(B) * n->lv[cv->level].H * n->lv[cv->level].W;
         work = std::max(work, lbm::nn::wgrad_plan(P, cv->cin, cv->cout, cv->taps).elems);
+        // split-K partial sums of the forward and of the input gradient (channel roles exchanged)
+        work = std::max(work, lbm::nn::fwd_split_elems(P, cv->cin, cv->cout, cv->taps));
+        work = std::max(work, lbm::nn::fwd_split_elems(P, cv->cout, cv->cin, cv->taps));
     }
+    n->work_elems = work;
     const size_t px0 = B * c.height * c.width;
     ok = ok && nn_alloc(n, &n->dz, max_act) && nn_alloc(n, &n->work, work) && nn_alloc(n, &n->part, px0 / 256 + 1) &&
          nn_alloc(n, &n->yout, px0 * kOutPad) && nn_alloc(n, &n->g_out, px0 * kOutPad) && nn_alloc(n, &n->d_red, 2) &&
@@ -1088,7 +1214,7 @@ lbm_status lbm_nn_forward(lbm_nn* n, const void* x, float* y, int32_t batch)
         LBM_HIP_TRY(fwd(n, v.c2, cs(v.e1, v.C), skip, nullptr, N, v.H, v.W, true));
         if (l < L - 1) {
             Level& nx = n->lv[l + 1];
-            hipLaunchKernelGGL(lbm::nn::k_pool_fwd, dim3(lbm::nn::blocks(size_t(N) * nx.H * nx.W * v.C)), dim3(256), 0,
+            hipLaunchKernelGGL(lbm::nn::k_pool_fwd, dim3(lbm::nn::blocks(size_t(N) * nx.H * nx.W * v.C / 8)), dim3(256), 0,
                                n->stream, CSlice{skip.p, skip.cs, skip.co}, sl(nx.in, v.C), N, v.H, v.W, v.C);
             LBM_HIP_TRY(hipGetLastError());
         }
@@ -1098,7 +1224,7 @@ lbm_status lbm_nn_forward(lbm_nn* n, const void* x, float* y, int32_t batch)
         const Level& below = n->lv[l + 1];
         const int cup = chan(n, l + 1), ccat = cup + v.C;
         const CSlice src = l == L - 2 ? cs(below.e2, below.C) : cs(below.d2o, below.C);
-        hipLaunchKernelGGL(lbm::nn::k_up_fwd, dim3(lbm::nn::blocks(size_t(N) * v.H * v.W * cup)), dim3(256), 0,
+        hipLaunchKernelGGL(lbm::nn::k_up_fwd, dim3(lbm::nn::blocks(size_t(N) * v.H * v.W * cup / 8)), dim3(256), 0,
                            n->stream, src, sl(v.cat, ccat, 0), N, below.H, below.W, cup);
         LBM_HIP_TRY(hipGetLastError());
         LBM_HIP_TRY(fwd(n, v.d1, cs(v.cat, ccat), sl(v.d1o, v.C), nullptr, N, v.H, v.W, true));
@@ -1136,7 +1262,7 @@ lbm_status lbm_nn_backward(lbm_nn* n, const float* target, const uint8_t* mask, 
     const Slice g_top = L == 1 ? sl(v0.g_e2, v0.C) : sl(v0.g_d2o, v0.C);
     LBM_HIP_TRY(wgrad(n, n->out, top, cs(n->g_out, kOutPad), N, v0.H, v0.W));
     LBM_HIP_TRY(lbm::nn::conv_dgrad(cs(n->g_out, kOutPad), n->out.wt, g_top, N, v0.H, v0.W, n->out.cin, n->out.cout,
-                                    1, false, n->stream));
+                                    1, false, n->stream, n->work, n->work_elems));
     // decoder, level 0 up to the level above the bottleneck
     for (int l = 0; l <= L - 2; ++l) {
         Level& v = n->lv[l];
@@ -1148,7 +1274,7 @@ lbm_status lbm_nn_backward(lbm_nn* n, const float* target, const uint8_t* mask, 
                                   v.H, v.W));
         // upsampled part of the concatenation -> gradient of the level below's output
         const Slice gsrc = l == L - 2 ? sl(below.g_e2, below.C) : sl(below.g_d2o, below.C);
-        hipLaunchKernelGGL(lbm::nn::k_up_bwd, dim3(lbm::nn::blocks(size_t(N) * below.H * below.W * cup)), dim3(256),
+        hipLaunchKernelGGL(lbm::nn::k_up_bwd, dim3(lbm::nn::blocks(size_t(N) * below.H * below.W * cup / 8)), dim3(256),
                            0, n->stream, cs(v.g_cat, ccat, 0), gsrc, N, below.H, below.W, cup);
         LBM_HIP_TRY(hipGetLastError());
     }
@@ -1165,7 +1291,7 @@ lbm_status lbm_nn_backward(lbm_nn* n, const float* target, const uint8_t* mask, 
         if (l > 0) {
             Level& up = n->lv[l - 1];
             const Slice g_skip = sl(up.g_cat, chan(n, l) + up.C, chan(n, l));
-            hipLaunchKernelGGL(lbm::nn::k_pool_bwd_add, dim3(lbm::nn::blocks(size_t(N) * up.H * up.W * up.C)),
+            hipLaunchKernelGGL(lbm::nn::k_pool_bwd_add, dim3(lbm::nn::blocks(size_t(N) * up.H * up.W * up.C / 8)),
                                dim3(256), 0, n->stream, cs(v.g_in, v.cin), g_skip, N, up.H, up.W, up.C);
             LBM_HIP_TRY(hipGetLastError());
         }
