@@ -187,13 +187,14 @@ def batched_sweep(steps=2000, solve_cap=100_000, tol=1e-8):
 
 def warm_start(n_eval=40, tol=1e-8):
     """Learned warm start against rest on held-out 256^2 random-cylinder problems (FP64 solves to
-    residual <= tol; wall time includes features, inference, fields and initialisation), and the
-    throughput of the network's forward pass on the matrix cores."""
+    residual <= tol; wall time includes features, inference, fields and initialisation; the
+    prediction starts the lattice with the non-equilibrium stress, and the steps from its f^eq alone
+    are reported beside), and the throughput of the network's forward pass on the matrix cores."""
     import torch
     from paper_2012_14707_amd import warmstart as W
     model = W.Model.load(W.DEFAULT_MODEL, max_batch=8)
     pbs = W.instances(W.TEST_SEEDS[:n_eval], workers=1)
-    rows = [W.compare(pb, model, tol) for pb in pbs]
+    rows = [W.compare(pb, model, tol, also_feq=True) for pb in pbs]
     out = W.summarize(rows)
     # forward pass of a batch of 8 images, timed with HIP events on the network's stream
     x = torch.zeros((8, W.SIDE, W.SIDE, W.IN_PAD), dtype=torch.bfloat16, device="cuda")

@@ -185,6 +185,16 @@ lbm_status lbm_init_rest(lbm_ctx *ctx);
  * reported by the next lbm_residual as LBM_E_UNSTABLE. */
 lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy, int32_t device_ptrs);
 
+/* lbm_init_fields plus a non-equilibrium part: at fluid nodes f_i = f_i^eq(rho, u - a/2) + f_i^neq with
+ * f^neq = M^-1 (0, 0, 0, 0, 0, 0, 0, p_xx, p_xy) (M of Sec. II), the first-order Chapman-Enskog
+ * stress of the given velocity field under the shear relaxation time tau_s of Eq. (tKnrela):
+ *   p_xx = -(2/3) tau_s rho (d_x u_x - d_y u_y),   p_xy = -(1/3) tau_s rho (d_x u_y + d_y u_x).
+ * Derivatives are differences over the fluid neighbours (central; one-sided next to a solid site;
+ * 0 with no fluid neighbour along that axis).  A steady flow has this stress, so starting from a
+ * good estimate of (rho, u) the lattice begins closer to its steady state than from f^eq alone.
+ * Arguments, layout and ownership as lbm_init_fields. */
+lbm_status lbm_init_fields_neq(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy, int32_t device_ptrs);
+
 /* Advances nsteps >= 0 time steps: per fluid node, collision in moment space (Eqs. (LBEColli),
  * (LBEforce), (MomentPost)) fused with streaming, and for each wall link the boundary value of
  * Eq. (EqNewBDSC).  Asynchronous on the context's stream. */

@@ -64,6 +64,7 @@ def _lib(variant="ld"):
     lib.ora_destroy.restype = None
     lib.ora_init_rest.argtypes = [vp]
     lib.ora_init_fields.argtypes = [vp, _DP, _DP, _DP]
+    lib.ora_init_fields_neq.argtypes = [vp, _DP, _DP, _DP]
     lib.ora_step.argtypes = [vp, C.c_int64]
     lib.ora_moments.argtypes = [vp, _DP, _DP, _DP]
     lib.ora_residual.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -173,9 +174,11 @@ class Oracle:
     def init_rest(self):
         self._lib.ora_init_rest(self._h)
 
-    def init_fields(self, rho, ux, uy):
+    def init_fields(self, rho, ux, uy, neq=False):
+        """f^eq(rho, u - a/2); with neq, plus the first-order non-equilibrium stress of u's gradients."""
         c = lambda a: np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
-        self._lib.ora_init_fields(self._h, c(rho), c(ux), c(uy))
+        fn = self._lib.ora_init_fields_neq if neq else self._lib.ora_init_fields
+        fn(self._h, c(rho), c(ux), c(uy))
 
     def step(self, n=1):
         self._lib.ora_step(self._h, int(n))

@@ -531,6 +531,47 @@ int ora_init_fields(ora_ctx *o, const double *rho, const double *ux, const doubl
     return ORA_OK;
 }
 
+/* Difference quotient of a site field phi along (dx, dy) at the fluid site (x, y), from its fluid
+ * neighbours only: central where both are fluid, one-sided where one is, zero where neither is. */
+static real fluid_diff(const ora_ctx *o, const double *phi, int x, int y, int dx, int dy)
+{
+    const int64_t s = (int64_t)y * o->nx + x;
+    const int64_t sp = neighbour(o, x, y, dx, dy), sm = neighbour(o, x, y, -dx, -dy);
+    const int fp = sp >= 0 && !o->solid[sp], fm = sm >= 0 && !o->solid[sm];
+    if (fp && fm) return ((real)phi[sp] - (real)phi[sm]) / 2.0L;
+    if (fp) return (real)phi[sp] - (real)phi[s];
+    if (fm) return (real)phi[s] - (real)phi[sm];
+    return 0.0L;
+}
+
+/* Initial fields with a non-equilibrium part: f = f^eq(rho, u - a/2) of Eq. (LBEequi) plus the
+ * first-order Chapman-Enskog non-equilibrium of the stress moments (rows 7 and 8 of M, Sec. II),
+ * which the shear rate relaxes at s_s = 1 / tau_s of Eq. (tKnrela):
+ *   m_pxx = -(2/3) tau_s rho (d_x u_x - d_y u_y),   m_pxy = -(1/3) tau_s rho (d_x u_y + d_y u_x),
+ * the pre-collision stress of a flow with those gradients (the other moments' first-order parts
+ * vanish for an incompressible velocity field), mapped back with the inverse of M.  Derivatives are
+ * fluid-neighbour differences of the given u. */
+int ora_init_fields_neq(ora_ctx *o, const double *rho, const double *ux, const double *uy)
+{
+    ora_init_fields(o, rho, ux, uy);
+    for (int y = 0; y < o->ny; ++y)
+        for (int x = 0; x < o->nx; ++x) {
+            const int64_t s = (int64_t)y * o->nx + x;
+            if (o->solid[s]) continue;
+            const real dxux = fluid_diff(o, ux, x, y, 1, 0), dyux = fluid_diff(o, ux, x, y, 0, 1);
+            const real dxuy = fluid_diff(o, uy, x, y, 1, 0), dyuy = fluid_diff(o, uy, x, y, 0, 1);
+            real m[9] = {0.0L, 0.0L, 0.0L, 0.0L, 0.0L, 0.0L, 0.0L, 0.0L, 0.0L};
+            m[7] = -(2.0L / 3.0L) * o->tau_s * (real)rho[s] * (dxux - dyuy);
+            m[8] = -(1.0L / 3.0L) * o->tau_s * (real)rho[s] * (dxuy + dyux);
+            for (int i = 0; i < 9; ++i) {
+                real acc = 0.0L;
+                for (int k = 0; k < 9; ++k) acc += o->minv[i][k] * m[k];
+                o->f[s * 9 + i] += acc;
+            }
+        }
+    return ORA_OK;
+}
+
 /* Links: (x, y) of the fluid node, dir = direction from the fluid node toward the wall
  * (the paper's ibar), q = distance ratio gamma in (0, 1], (ubx, uby) = wall velocity at x_b. */
 int ora_create(const ora_params *p, const uint8_t *solid, int64_t nlinks, const int32_t *lx, const int32_t *ly,

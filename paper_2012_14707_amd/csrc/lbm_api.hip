@@ -373,7 +373,9 @@ lbm_status lbm_init_rest(lbm_ctx* c)
     return LBM_OK;
 }
 
-lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t device_ptrs)
+namespace {
+lbm_status init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t device_ptrs,
+                       double neq_tau)
 {
     if (!c || !rho || !ux || !uy) return fail(LBM_E_INVAL, "null argument");
     DeviceGuard g(c->device);
@@ -393,9 +395,21 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, cons
         dv = c->d_stage + 2 * size_t(n);
     }
     LBM_HIP_TRY(lbm::launch_init_fields(c->fp32(), c->geo(), c->d_buf[0], c->d_link[0], dr, du, dv, c->pr.p.rho0,
-                                        c->pr.p.ax, c->pr.p.ay, c->stream));
+                                        c->pr.p.ax, c->pr.p.ay, neq_tau, c->stream));
     if (!device_ptrs) LBM_HIP_TRY(hipStreamSynchronize(c->stream));  // the host arrays may go away
     return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t device_ptrs)
+{
+    return init_fields(c, rho, ux, uy, device_ptrs, 0.0);
+}
+
+lbm_status lbm_init_fields_neq(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t device_ptrs)
+{
+    if (!c) return fail(LBM_E_INVAL, "null context");
+    return init_fields(c, rho, ux, uy, device_ptrs, c->pr.g.tau_s);
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)

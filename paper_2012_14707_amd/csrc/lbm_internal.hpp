@@ -171,8 +171,10 @@ hipError_t launch_residual_batch_f32(const BatchReduceArgs<float>& a, int block,
 hipError_t launch_fill_zero(void* ptr, uint64_t bytes, hipStream_t stream);
 // Copies bytes (a multiple of 16; both pointers 16-byte aligned) from src to dst.
 hipError_t launch_stream_copy(void* dst, const void* src, uint64_t bytes, hipStream_t stream);
+// f = f^eq(rho, u - a/2) at fluid sites; with neq_tau = tau_s > 0 plus the first-order
+// non-equilibrium of the stress moments from the fluid-neighbour differences of u.
 hipError_t launch_init_fields(bool fp32, const Geo& g, void* pop, void* link, const double* rho, const double* ux,
-                              const double* uy, double rho0, double ax, double ay, hipStream_t stream);
+                              const double* uy, double rho0, double ax, double ay, double neq_tau, hipStream_t stream);
 hipError_t launch_moments(bool fp32, const Geo& g, const void* pop, const void* link, double* rho, double* ux,
                           double* uy, double rho0, double ax, double ay, hipStream_t stream);
 // Residual partial sums (|du|^2, |u|^2, sum of density deviations) and the fixed-order final

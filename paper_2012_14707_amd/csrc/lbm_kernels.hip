@@ -1076,7 +1076,7 @@ __global__ void __launch_bounds__(256) k_fill_zero_bytes(uint8_t* p, uint64_t n)
 template <typename T>
 __global__ void __launch_bounds__(256) k_init_fields(const Geo g, T* pop, T* lnk, const double* rho_in,
                                                      const double* ux_in, const double* uy_in, double rho0,
-                                                     double ax, double ay)
+                                                     double ax, double ay, double neq_tau)
 {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     const SiteLinks sl = site_links(g, s);
@@ -1087,8 +1087,26 @@ __global__ void __launch_bounds__(256) k_init_fields(const Geo g, T* pop, T* lnk
     const double vx = ux_in[s] - 0.5 * ax, vy = uy_in[s] - 0.5 * ay;
     const double v2 = vx * vx + vy * vy;
     const uint64_t N = g.ps;
-    auto dev = [&](double w, double cv) {
-        return static_cast<T>(w * (rho - rho0) + w * rho * (3.0 * cv + 4.5 * cv * cv - 1.5 * v2));
+    // optional first-order non-equilibrium of the stress moments (neq_tau = tau_s > 0):
+    // pxx = -(2/3) tau_s rho (d_x u_x - d_y u_y), pxy = -(1/3) tau_s rho (d_x u_y + d_y u_x), with the
+    // derivatives taken from the fluid neighbours (central, one-sided next to a solid site, else 0);
+    // f^neq = M^-1 (0, .., 0, pxx, pxy) gives +-pxx / 4 on the axis directions and +-pxy / 4 on the
+    // diagonals
+    double pxx = 0.0, pxy = 0.0;
+    if (neq_tau > 0.0) {
+        auto diff = [&](const double* f, uint32_t sp, uint32_t sm) {
+            const bool fp = g.flags[sp] != kSolid, fm = g.flags[sm] != kSolid;
+            return (fp && fm) ? (f[sp] - f[sm]) * 0.5 : (fp ? f[sp] - f[s] : (fm ? f[s] - f[sm] : 0.0));
+        };
+        const uint32_t e = b.row + b.xp, w = b.row + b.xm, nn = b.rowp + b.x, so = b.rowm + b.x;
+        const double dxux = diff(ux_in, e, w), dyux = diff(ux_in, nn, so);
+        const double dxuy = diff(uy_in, e, w), dyuy = diff(uy_in, nn, so);
+        pxx = -(2.0 / 3.0) * neq_tau * rho * (dxux - dyuy);
+        pxy = -(1.0 / 3.0) * neq_tau * rho * (dxuy + dyux);
+    }
+    const double qa = 0.25 * pxx, qd = 0.25 * pxy;
+    auto dev = [&](double w, double cv, double nq) {
+        return static_cast<T>(w * (rho - rho0) + w * rho * (3.0 * cv + 4.5 * cv * cv - 1.5 * v2) + nq);
     };
     auto put = [&](int i, int d, uint32_t up, T v) {
         if (fl & (1u << (d - 1)))
@@ -1096,15 +1114,15 @@ __global__ void __launch_bounds__(256) k_init_fields(const Geo g, T* pop, T* lnk
         else
             pop[i * N + up] = v;
     };
-    pop[s] = dev(4.0 / 9.0, 0.0);
-    put(1, 3, b.row + b.xm, dev(1.0 / 9.0, vx));
-    put(2, 4, b.rowm + b.x, dev(1.0 / 9.0, vy));
-    put(3, 1, b.row + b.xp, dev(1.0 / 9.0, -vx));
-    put(4, 2, b.rowp + b.x, dev(1.0 / 9.0, -vy));
-    put(5, 7, b.rowm + b.xm, dev(1.0 / 36.0, vx + vy));
-    put(6, 8, b.rowm + b.xp, dev(1.0 / 36.0, -vx + vy));
-    put(7, 5, b.rowp + b.xp, dev(1.0 / 36.0, -vx - vy));
-    put(8, 6, b.rowp + b.xm, dev(1.0 / 36.0, vx - vy));
+    pop[s] = dev(4.0 / 9.0, 0.0, 0.0);
+    put(1, 3, b.row + b.xm, dev(1.0 / 9.0, vx, qa));
+    put(2, 4, b.rowm + b.x, dev(1.0 / 9.0, vy, -qa));
+    put(3, 1, b.row + b.xp, dev(1.0 / 9.0, -vx, qa));
+    put(4, 2, b.rowp + b.x, dev(1.0 / 9.0, -vy, -qa));
+    put(5, 7, b.rowm + b.xm, dev(1.0 / 36.0, vx + vy, qd));
+    put(6, 8, b.rowm + b.xp, dev(1.0 / 36.0, -vx + vy, -qd));
+    put(7, 5, b.rowp + b.xp, dev(1.0 / 36.0, -vx - vy, qd));
+    put(8, 6, b.rowp + b.xm, dev(1.0 / 36.0, vx - vy, -qd));
 }
 
 template <typename T>
@@ -1459,15 +1477,15 @@ hipError_t launch_stream_copy(void* dst, const void* src, uint64_t bytes, hipStr
 }
 
 hipError_t launch_init_fields(bool fp32, const Geo& g, void* pop, void* link, const double* rho, const double* ux,
-                              const double* uy, double rho0, double ax, double ay, hipStream_t stream)
+                              const double* uy, double rho0, double ax, double ay, double neq_tau, hipStream_t stream)
 {
     const dim3 grid(ceil_div(g.n, 256)), blk(256);
     if (fp32)
         hipLaunchKernelGGL(k_init_fields<float>, grid, blk, 0, stream, g, static_cast<float*>(pop),
-                           static_cast<float*>(link), rho, ux, uy, rho0, ax, ay);
+                           static_cast<float*>(link), rho, ux, uy, rho0, ax, ay, neq_tau);
     else
         hipLaunchKernelGGL(k_init_fields<double>, grid, blk, 0, stream, g, static_cast<double*>(pop),
-                           static_cast<double*>(link), rho, ux, uy, rho0, ax, ay);
+                           static_cast<double*>(link), rho, ux, uy, rho0, ax, ay, neq_tau);
     return hipGetLastError();
 }
 

@@ -82,6 +82,7 @@ SIGNATURES = {
     "lbm_link_coeffs": (C.c_int32, [_VP, _VP]),
     "lbm_init_rest": (C.c_int32, [_VP]),
     "lbm_init_fields": (C.c_int32, [_VP, _VP, _VP, _VP, C.c_int32]),
+    "lbm_init_fields_neq": (C.c_int32, [_VP, _VP, _VP, _VP, C.c_int32]),
     "lbm_step": (C.c_int32, [_VP, C.c_int64]),
     "lbm_moments": (C.c_int32, [_VP, _VP, _VP, _VP, C.c_int32]),
     "lbm_residual": (C.c_int32, [_VP, _DPTR, _DPTR]),
@@ -263,18 +264,20 @@ class Lattice:
     def init_rest(self):
         _check(self._lib.lbm_init_rest(self._h))
 
-    def init_fields(self, rho, ux, uy):
-        """rho, ux, uy: torch float64 CUDA tensors or numpy float64 arrays of the lattice shape."""
+    def init_fields(self, rho, ux, uy, neq=False):
+        """rho, ux, uy: torch float64 CUDA tensors or numpy float64 arrays of the lattice shape;
+        neq: add the first-order non-equilibrium stress (lbm_init_fields_neq)."""
         import torch
+        fn = self._lib.lbm_init_fields_neq if neq else self._lib.lbm_init_fields
         if isinstance(rho, torch.Tensor):
             t = [x.contiguous() for x in (rho, ux, uy)]
             for x in t:
                 if x.dtype != torch.float64 or not x.is_cuda or tuple(x.shape) != self.shape:
                     raise ValueError("fields must be float64 CUDA tensors of the lattice shape")
-            _check(self._lib.lbm_init_fields(self._h, *[C.c_void_p(x.data_ptr()) for x in t], 1))
+            _check(fn(self._h, *[C.c_void_p(x.data_ptr()) for x in t], 1))
         else:
             a = [np.ascontiguousarray(x, dtype=np.float64).reshape(self.shape) for x in (rho, ux, uy)]
-            _check(self._lib.lbm_init_fields(self._h, *[x.ctypes.data_as(C.c_void_p) for x in a], 0))
+            _check(fn(self._h, *[x.ctypes.data_as(C.c_void_p) for x in a], 0))
 
     def step(self, n=1):
         _check(self._lib.lbm_step(self._h, int(n)))

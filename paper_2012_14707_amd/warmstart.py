@@ -353,8 +353,11 @@ def evaluate_loss(model, data, batch=None):
 # ------------------------------------------------------------------------------------ solve
 
 def solve(pb, model=None, tol=1e-8, check_every=100, max_steps=1_000_000, precision="fp64", growth=10.0,
-          lattice=None):
+          lattice=None, neq=True):
     """Runs one problem to residual <= tol from rest (model None) or from the model's prediction.
+
+    The predicted (rho, u) become f^eq plus, with neq, the first-order non-equilibrium stress of the
+    predicted velocity gradients (lbm_init_fields_neq), which a steady flow carries.
 
     Wall time covers everything after the lattice exists: for a warm start the upload of mask and
     links, features, the forward pass, the fields, the initialisation, and every step and residual
@@ -376,7 +379,7 @@ def solve(pb, model=None, tol=1e-8, check_every=100, max_steps=1_000_000, precis
             warm = False
             lat.init_rest()
         else:
-            lat.init_fields(rho, ux, uy)
+            lat.init_fields(rho, ux, uy, neq=neq)
     else:
         lat.init_rest()
     torch.cuda.synchronize()
@@ -405,11 +408,16 @@ def solve(pb, model=None, tol=1e-8, check_every=100, max_steps=1_000_000, precis
     return dict(steps=steps, wall=wall, init=t_init, residual=res, fallback=fallback, converged=res <= tol), lat
 
 
-def compare(pb, model, tol=1e-8, check_every=100, max_steps=1_000_000, precision="fp64"):
-    """Rest and warm solves of one problem, and the difference of their converged velocities."""
+def compare(pb, model, tol=1e-8, check_every=100, max_steps=1_000_000, precision="fp64", neq=True, also_feq=False):
+    """Rest and warm solves of one problem, and the difference of their converged velocities.
+    With also_feq, a third solve starts from the prediction's f^eq alone (warm_feq_* entries)."""
     rest, lat = solve(pb, None, tol, check_every, max_steps, precision)
     _, ux_r, uy_r = lat.moments_host()
-    warm, lat = solve(pb, model, tol, check_every, max_steps, precision, lattice=lat)
+    extra = {}
+    if also_feq:
+        feq, lat = solve(pb, model, tol, check_every, max_steps, precision, lattice=lat, neq=False)
+        extra = dict(warm_feq_steps=feq["steps"], warm_feq_wall=feq["wall"])
+    warm, lat = solve(pb, model, tol, check_every, max_steps, precision, lattice=lat, neq=neq)
     _, ux_w, uy_w = lat.moments_host()
     lat.close()
     umax = max(np.abs(ux_r).max(), np.abs(uy_r).max())
@@ -417,7 +425,7 @@ def compare(pb, model, tol=1e-8, check_every=100, max_steps=1_000_000, precision
     return dict(seed=pb["meta"].get("seed"), kn=pb["params"]["kn"], porosity=pb["meta"].get("porosity"),
                 rest_steps=rest["steps"], rest_wall=rest["wall"], warm_steps=warm["steps"], warm_wall=warm["wall"],
                 warm_init=warm["init"], fallback=warm["fallback"], converged=rest["converged"] and warm["converged"],
-                u_rel_diff=diff)
+                u_rel_diff=diff, **extra)
 
 
 def summarize(rows):
@@ -427,15 +435,19 @@ def summarize(rows):
     ww = np.array([r["warm_wall"] for r in rows])
     ratio = ws / rs
     wr = ww / rw
-    return dict(n=len(rows), rest_steps_median=float(np.median(rs)), warm_steps_median=float(np.median(ws)),
-                warm_init_ms_median=float(np.median([r.get("warm_init", 0.0) for r in rows]) * 1e3),
-                step_ratio_median=float(np.median(ratio)), step_ratio_mean=float(ratio.mean()),
-                step_ratio_worst=float(ratio.max()), wall_ratio_median=float(np.median(wr)),
-                wall_ratio_mean=float(wr.mean()), wall_ratio_worst=float(wr.max()),
-                rest_wall_total=float(rw.sum()), warm_wall_total=float(ww.sum()),
-                fallbacks=sum(r["fallback"] is not None for r in rows),
-                all_converged=all(r["converged"] for r in rows),
-                u_rel_diff_max=float(max(r["u_rel_diff"] for r in rows)))
+    out = dict(n=len(rows), rest_steps_median=float(np.median(rs)), warm_steps_median=float(np.median(ws)),
+               warm_init_ms_median=float(np.median([r.get("warm_init", 0.0) for r in rows]) * 1e3),
+               step_ratio_median=float(np.median(ratio)), step_ratio_mean=float(ratio.mean()),
+               step_ratio_worst=float(ratio.max()), wall_ratio_median=float(np.median(wr)),
+               wall_ratio_mean=float(wr.mean()), wall_ratio_worst=float(wr.max()),
+               rest_wall_total=float(rw.sum()), warm_wall_total=float(ww.sum()),
+               fallbacks=sum(r["fallback"] is not None for r in rows),
+               all_converged=all(r["converged"] for r in rows),
+               u_rel_diff_max=float(max(r["u_rel_diff"] for r in rows)))
+    if all("warm_feq_steps" in r for r in rows):
+        fr = np.array([r["warm_feq_steps"] for r in rows], float) / rs
+        out.update(feq_init_step_ratio_median=float(np.median(fr)), feq_init_step_ratio_worst=float(fr.max()))
+    return out
 
 
 def main(argv=None):

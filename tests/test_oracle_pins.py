@@ -13,6 +13,7 @@ dropped term, a wrong sign or index, a transposed operand) breaks at least one o
   - full chain at the paper's prescription ....... test_config1_analytic_profile
   - convergence residual and mass ................ test_residual_from_two_snapshots
   - initial fields (half-force shift) ............ test_init_fields_half_force_shift
+  - initial fields with the non-equilibrium stress test_init_fields_neq_matches_a_steady_state
 """
 import math
 
@@ -342,6 +343,42 @@ def test_init_fields_half_force_shift():
     r2, ux2, uy2 = o.moments()
     assert np.allclose(r2, rho, rtol=1e-15) and np.allclose(ux2, ux, rtol=0, atol=1e-16)
     assert np.allclose(uy2, uy, rtol=0, atol=1e-16)
+
+
+def test_init_fields_neq_matches_a_steady_state():
+    """The non-equilibrium initial fields: the stress moment of the first-order Chapman-Enskog part,
+    p_xy = -(1/3) tau_s rho d_y u_x, equals the one a converged channel carries (M of Sec. II applied
+    on the test side to the oracle's steady populations), and a restart from the steady (rho, u) with
+    that part sits much closer to the steady state than one from f^eq alone."""
+    pb = G.channel(40, nx=4, gamma=0.3, kn=0.05, ax=1e-5)
+    o = oracle.Oracle(pb["params"], pb["solid"], pb["links"])
+    o.run_to_steady(1e-13, 100, max_steps=400_000)
+    f_steady = o.get_f()
+    rho, ux, uy = o.moments()
+    ts = o.globals["tau_s"]
+    # the steady state's own p_xy non-equilibrium against the formula at interior rows
+    cu = CX[None, None, :] * ux[..., None] + CY[None, None, :] * uy[..., None]
+    feq = WI * rho[..., None] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (ux ** 2 + uy ** 2)[..., None])
+    pxy = ((f_steady - feq) * (CX * CY)[None, None, :]).sum(-1)
+    j = np.arange(3, 39)
+    pred = -ts / 3 * rho[j, 0] * (ux[j + 1, 0] - ux[j - 1, 0]) / 2
+    assert np.max(np.abs(pxy[j, 0] - pred)) < 1e-6 * np.max(np.abs(pred))
+    # restarts from the steady moments
+    res = {}
+    for neq in (False, True):
+        r = oracle.Oracle(pb["params"], pb["solid"], pb["links"])
+        r.init_fields(rho, ux - 0.0, uy, neq=neq)
+        r.step(1)
+        r.step(1)
+        res[neq] = r.residual()[0]
+        if neq:
+            # the initialised state's stress moment is the steady one in the interior
+            r.init_fields(rho, ux, uy, neq=True)
+            g = r.get_f()
+            feq_s = WI * rho[..., None] * (1 + 3 * (cu - 0) + 4.5 * cu ** 2 - 1.5 * (ux ** 2 + uy ** 2)[..., None])
+            pxy_init = (g * (CX * CY)[None, None, :]).sum(-1) - (feq_s * (CX * CY)[None, None, :]).sum(-1)
+            assert np.max(np.abs(pxy_init[j, 0] - pxy[j, 0])) < 1e-3 * np.max(np.abs(pxy[j, 0]))
+    assert res[True] < 0.2 * res[False], res
 
 
 def test_mass_periodic_and_halfway():
