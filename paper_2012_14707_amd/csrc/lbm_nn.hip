@@ -68,71 +68,109 @@ __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, i
     x = r - y * W;
 }
 
+// 16 zero bytes: the source of the operand chunks that lie outside the image (zero padding), past
+// the end of K or past the last pixel or output channel, for the direct-to-LDS loads below.
+__device__ __align__(16) uint4 g_zero16 = {0u, 0u, 0u, 0u};
+
+// LDS slot of 16-byte K group q of operand row r in a stage: rows of four groups (64 bytes), the
+// group index XOR-swizzled by row so that the 16-byte reads of the MFMA operands (16 consecutive
+// rows, one group) fall in distinct banks.
+__device__ __forceinline__ int conv_slot(int r, int q) { return r * 4 + (q ^ (((r >> 1) ^ (r >> 3)) & 3)); }
+
 // out[p][co] = act(bias[co] + sum_{tap, ci} x[p + off(tap)][ci] w[tap][co][ci]), with zero padding
 // or periodic wrap-around at the image edges.
 // One block of four waves computes a BM-pixel x BN-channel tile (the launcher picks the largest of
 // 128 x 64, 128 x 32, 64 x 64, 64 x 32 that still gives enough blocks to fill the chip); the waves
-// form a WGM x WGN grid and each multiplies a (BM / WGM) x (BN / WGN) part with 16x16x32 MFMAs.  K runs over (tap, ci);
-// Cin is a multiple of 8 so every 8-wide K group lies in one tap and is one 16-byte load.  The
-// next K step's operands are loaded into registers while the current one is multiplied, and LDS
-// is double-buffered, so there is one barrier per K step.
-template <int TAPS, int BM, int BN>
+// form a WGM x WGN grid and each multiplies a (BM / WGM) x (BN / WGN) part with 16x16x32 MFMAs.  K
+// runs over (tap, ci) in steps of TK; Cin is a multiple of 8, so every 8-wide K group lies in one tap
+// and is one 16-byte chunk.  NS-stage pipeline: the operand chunks go from global memory straight
+// into LDS (16-byte direct loads, no registers), NS - 1 K steps ahead of the multiply, with one
+// barrier per K step.  Thread t loads, for each K step, the 16-byte group q(t) of operand rows
+// t / 4 + 64 j, whose LDS slots are exactly the 16-byte positions 16 (t + 256 j) that the direct
+// load of its wave writes (lane order).  The load addresses advance incrementally with K; the
+// per-step integer work is a few adds (a division per step made the kernel bound by vector issue,
+// with only 4-8 MFMAs per wave per step).
+template <int TAPS, int BM, int BN, int NS>
 __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
 {
-    constexpr int WGN = BN >= 64 ? 2 : 1, WGM = 4 / WGN;         // wave grid
-    constexpr int MI = BM / WGM / 16, NJ = BN / WGN / 16;         // MFMA tiles per wave
-    constexpr int AR = BM / 64;            // A rows loaded per thread per K step
-    constexpr int BR = (BN * 4 + 255) / 256;  // B rows per thread (1; threads beyond BN * 4 idle)
-    __shared__ __align__(16) bf16 As[2][BM * LDK];
-    __shared__ __align__(16) bf16 Bs[2][BN * LDK];
+    constexpr int WGN = BN >= 64 ? 2 : 1, WGM = 4 / WGN;
+    constexpr int MI = BM / WGM / 16, NJ = BN / WGN / 16;
+    constexpr int AJ = BM / 64;                   // A rows per thread per K step
+    constexpr int BT = BN * 4;                    // threads that load a B group (BN * 4 <= 256)
+    static_assert(BT <= 256 && BT % 64 == 0, "B groups fill whole waves");
+    extern __shared__ __align__(16) unsigned char smem[];
+    bf16* As = reinterpret_cast<bf16*>(smem);                 // [NS][BM * 32]
+    bf16* Bs = As + NS * BM * 32;                              // [NS][BN * 32]
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int P = a.N * a.H * a.W;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    // this block's K range: the whole of it, or split blockIdx.z of a split-K launch
     const int kb = a.part ? blockIdx.z * a.kper : 0;
     const int K = a.part ? min(TAPS * a.Cin, kb + a.kper) : TAPS * a.Cin;
-    const int lg = tid % 4;  // 8-wide K group loaded by this thread
-    int pn[AR], py[AR], px[AR];
-    bool pin[AR];
+    const int nsteps = (K - kb + TK - 1) / TK;
+    // this thread's K group (swizzled as the LDS slot it fills) and operand rows
+    const int q = (tid & 3) ^ (((tid >> 3) ^ (tid >> 5)) & 3);
+    int pn[AJ], py[AJ], px[AJ];
+    bool pin[AJ];
 #pragma unroll
-    for (int j = 0; j < AR; ++j) {
+    for (int j = 0; j < AJ; ++j) {
         const int p = m0 + tid / 4 + 64 * j;
         pin[j] = p < P;
         pn[j] = py[j] = px[j] = 0;
         if (pin[j]) decompose(p, a.H, a.W, pn[j], py[j], px[j]);
     }
-    const int co_l = n0 + tid / 4;
-    const bool b_thread = BR * 256 > tid && tid / 4 < BN;
+    const int co = n0 + tid / 4;
+    const bool b_loader = tid < BT;  // wave-uniform (BT is a multiple of 64)
+    const bf16* zero = reinterpret_cast<const bf16*>(&g_zero16);
 
-    bf16x8 ra[AR], rb;
-    auto load = [&](int k0) {
-        const int k = k0 + lg * 8;
-        const bool kin = k < K;
-        const int tap = kin ? k / a.Cin : 0, ci = kin ? k - tap * a.Cin : 0;
-        const int dy = (TAPS == 9 ? tap / 3 - 1 : 0), dx = (TAPS == 9 ? tap % 3 - 1 : 0);
+    // The K position of this thread's group walks forward by TK per step: (tap, ci) and the element
+    // offsets of the operand rows for the current tap are updated incrementally (no division per
+    // step); they change tap only every Cin / TK steps.
+    int kc = kb + q * 8;
+    int tap = kc / a.Cin, ci = kc - tap * a.Cin;
+    long aoff[AJ];
+    bool aval[AJ];
+    long boff = 0;
+    auto set_tap = [&](int t) __attribute__((always_inline)) {
+        const int dy = (TAPS == 9 ? t / 3 - 1 : 0), dx = (TAPS == 9 ? t % 3 - 1 : 0);
 #pragma unroll
-        for (int j = 0; j < AR; ++j) {
-            ra[j] = bf16x8{};
-            if (kin && pin[j]) {
-                int yy = py[j] + dy, xx = px[j] + dx;
-                if (a.periodic) {
-                    yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
-                    xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
-                }
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    ra[j] = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((pn[j] * a.H + yy) * a.W + xx) * a.x.cs +
-                                                             a.x.co + ci);
+        for (int j = 0; j < AJ; ++j) {
+            int yy = py[j] + dy, xx = px[j] + dx;
+            if (a.periodic) {
+                yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
             }
+            aval[j] = pin[j] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            aoff[j] = long((pn[j] * a.H + yy) * a.W + xx) * a.x.cs + a.x.co;
         }
-        rb = bf16x8{};
-        if (b_thread && kin && co_l < a.Cout)
-            rb = *reinterpret_cast<const bf16x8*>(a.w + (size_t(tap) * a.Cout + co_l) * a.Cin + ci);
+        boff = long(t * a.Cout + co) * a.Cin;
     };
-    auto stash = [&](int buf) {
+    set_tap(tap < TAPS ? tap : 0);
+
+    auto issue = [&](int step) __attribute__((always_inline)) {
+        const int stage = step % NS;
+        const bool kin = kc < K;
 #pragma unroll
-        for (int j = 0; j < AR; ++j)
-            *reinterpret_cast<bf16x8*>(&As[buf][(tid / 4 + 64 * j) * LDK + lg * 8]) = ra[j];
-        if (b_thread) *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * LDK + lg * 8]) = rb;
+        for (int j = 0; j < AJ; ++j) {
+            const bf16* src = (kin && aval[j]) ? a.x.p + aoff[j] + ci : zero;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(As + stage * BM * 32 +
+                                                                                              (256 * j + wave * 64) * 8),
+                                             16, 0, 0);
+        }
+        if (b_loader) {
+            const bf16* src = (kin && co < a.Cout) ? a.w + boff + ci : zero;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(Bs + stage * BN * 32 +
+                                                                                              wave * 64 * 8),
+                                             16, 0, 0);
+        }
+        kc += TK;
+        ci += TK;
+        if (ci >= a.Cin) {
+            do {
+                ci -= a.Cin;
+                ++tap;
+            } while (ci >= a.Cin);
+            if (tap < TAPS) set_tap(tap);
+        }
     };
 
     f4 acc[MI][NJ];
@@ -142,32 +180,43 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
         for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     const int wm = (wave / WGN) * (BM / WGM), wn = (wave % WGN) * (BN / WGN);
 
-    load(kb);
-    stash(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = kb; k0 < K; k0 += TK) {
-        const bool more = k0 + TK < K;
-        if (more) load(k0 + TK);
-        // A operand: lane holds row lane % 16, k = 8 (lane / 16) .. +7; B likewise by column
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nsteps) issue(s);
+    for (int s = 0; s < nsteps; ++s) {
+        // this wave's loads of step s have landed once at most the later steps' are outstanding
+        const int later = min(nsteps - 1 - s, NS - 2);
+        if (later >= NS - 2) {
+            if (b_loader) asm volatile("s_waitcnt vmcnt(%0)" ::"n"((NS - 2) * (AJ + 1)) : "memory");
+            else asm volatile("s_waitcnt vmcnt(%0)" ::"n"((NS - 2) * AJ) : "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        // A plain hardware barrier: the LDS data of step s came from the direct loads just waited
+        // for, and the loop writes LDS no other way, so the workgroup fence of __syncthreads (which
+        // would also wait for the loads still in flight for later steps) is not needed; the empty
+        // asm keeps the compiler from moving LDS accesses across it.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // every wave is past step s - 1: its stage takes the loads of step s + NS - 1
+        if (s + NS - 1 < nsteps) issue(s + NS - 1);
+        const bf16* A = As + (s % NS) * BM * 32;
+        const bf16* B = Bs + (s % NS) * BN * 32;
         bf16x8 fb[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
-            fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn + 16 * j + lane % 16) * LDK + 8 * (lane / 16)]);
+            fb[j] = *reinterpret_cast<const bf16x8*>(B + conv_slot(wn + 16 * j + lane % 16, lane / 16) * 8);
 #pragma unroll
         for (int i = 0; i < MI; ++i) {
-            const bf16x8 fa =
-                *reinterpret_cast<const bf16x8*>(&As[buf][(wm + 16 * i + lane % 16) * LDK + 8 * (lane / 16)]);
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(A + conv_slot(wm + 16 * i + lane % 16, lane / 16) * 8);
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
         }
-        if (more) stash(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
     }
     // result: lane holds column lane % 16, rows 4 (lane / 16) + r
-    if (a.part) {  // split K: raw partial sums; k_split_sum adds the splits, the bias and the activation
+    if (a.part) {
         float* out = a.part + size_t(blockIdx.z) * P * a.Cout;
 #pragma unroll
         for (int i = 0; i < MI; ++i)
@@ -201,8 +250,6 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
         }
 }
 
-// Epilogue of a split-K convolution: out[p][co] = act(bias[co] + sum over splits s, in order, of
-// part[s][p][co]).
 __global__ void __launch_bounds__(256) k_split_sum(const ConvArgs a, int splits)
 {
     const size_t P = size_t(a.N) * a.H * a.W;
@@ -663,6 +710,9 @@ inline unsigned blocks(size_t n) { return unsigned((n + 255) / 256); }
 
 // Splits of the K range for a convolution whose 64 x 64 grid has too few blocks to fill the chip:
 // enough splits for about 1024 blocks, at most 8, each at least 16 K steps long (1 = no split).
+// pipeline stages of the convolution kernel (3 measured faster than 2 or 4)
+constexpr int kConvStages = 3;
+
 int fwd_splits(long P, int Cin, int Cout, int taps)
 {
     const long tiles = ((P + 63) / 64) * ((Cout + 63) / 64);
@@ -692,10 +742,11 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         a.kper = ((K + splits - 1) / splits + TK - 1) / TK * TK;
         const int nsplit = (K + a.kper - 1) / a.kper;
         const dim3 grid(unsigned((P + 63) / 64), unsigned((Cout + 63) / 64), unsigned(nsplit));
+        const size_t lds = size_t(kConvStages) * (64 + 64) * 64;
         if (taps == 9)
-            hipLaunchKernelGGL((k_conv_fwd<9, 64, 64>), grid, dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_conv_fwd<9, 64, 64, kConvStages>), grid, dim3(256), lds, st, a);
         else
-            hipLaunchKernelGGL((k_conv_fwd<1, 64, 64>), grid, dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_conv_fwd<1, 64, 64, kConvStages>), grid, dim3(256), lds, st, a);
         hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
         return hipGetLastError();
     }
@@ -703,17 +754,17 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
     auto blocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
     auto go = [&](auto kern, int bm, int bn) {
         const dim3 grid(unsigned((P + bm - 1) / bm), unsigned((Cout + bn - 1) / bn));
-        hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(kern, grid, dim3(256), size_t(kConvStages) * (bm + bn) * 64, st, a);
     };
     const bool t9 = taps == 9;
     if (Cout >= 64 && blocks(128, 64) >= 1024)
-        t9 ? go(k_conv_fwd<9, 128, 64>, 128, 64) : go(k_conv_fwd<1, 128, 64>, 128, 64);
+        t9 ? go(k_conv_fwd<9, 128, 64, kConvStages>, 128, 64) : go(k_conv_fwd<1, 128, 64, kConvStages>, 128, 64);
     else if (Cout >= 64)
-        t9 ? go(k_conv_fwd<9, 64, 64>, 64, 64) : go(k_conv_fwd<1, 64, 64>, 64, 64);
+        t9 ? go(k_conv_fwd<9, 64, 64, kConvStages>, 64, 64) : go(k_conv_fwd<1, 64, 64, kConvStages>, 64, 64);
     else if (blocks(128, 32) >= 1024)
-        t9 ? go(k_conv_fwd<9, 128, 32>, 128, 32) : go(k_conv_fwd<1, 128, 32>, 128, 32);
+        t9 ? go(k_conv_fwd<9, 128, 32, kConvStages>, 128, 32) : go(k_conv_fwd<1, 128, 32, kConvStages>, 128, 32);
     else
-        t9 ? go(k_conv_fwd<9, 64, 32>, 64, 32) : go(k_conv_fwd<1, 64, 32>, 64, 32);
+        t9 ? go(k_conv_fwd<9, 64, 32, kConvStages>, 64, 32) : go(k_conv_fwd<1, 64, 32, kConvStages>, 64, 32);
     return hipGetLastError();
 }
 
