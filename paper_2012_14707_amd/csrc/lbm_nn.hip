@@ -231,6 +231,38 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
             }
         return;
     }
+    if (a.y.p && !a.yf && a.Cout % 8 == 0 && a.y.cs % 8 == 0 && a.y.co % 8 == 0) {
+        // bf16 output through LDS (free after the K loop): the tile is written back in rows of
+        // 16-byte chunks instead of one 2-byte store per accumulator element
+        constexpr int BNP = BN + 8;  // padded LDS row (a multiple of 16 bytes)
+        static_assert(BM * BNP * 2 <= NS * (BM + BN) * 64, "the output tile fits the operand stages");
+        bf16* Cs = reinterpret_cast<bf16*>(smem);
+        __syncthreads();  // every wave is done with the operand stages
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int cl = wn + 16 * j + lane % 16;
+                const float b = (a.bias && n0 + cl < a.Cout) ? a.bias[n0 + cl] : 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[i][j][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    Cs[(wm + 16 * i + 4 * (lane / 16) + r) * BNP + cl] = bf16(v);
+                }
+            }
+        __syncthreads();
+        constexpr int G = BN / 8;  // 8-channel chunks per tile row
+#pragma unroll
+        for (int c = tid; c < BM * G; c += 256) {
+            const int rl = c / G, g = c % G;
+            const int row = m0 + rl, col = n0 + 8 * g;
+            if (row < P && col < a.Cout)
+                *reinterpret_cast<bf16x8*>(a.y.p + size_t(row) * a.y.cs + a.y.co + col) =
+                    *reinterpret_cast<const bf16x8*>(Cs + rl * BNP + 8 * g);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
