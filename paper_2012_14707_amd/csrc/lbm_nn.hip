@@ -378,13 +378,21 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const WgradArgs a)
 }
 
 // grad[e] = sum_s partial[s][e], in split order (deterministic).
+// grad[e] = sum over k < nsplit of partial[k][e]: 32 elements per block, eight lanes per element
+// summing interleaved k, then a butterfly over the eight lanes (every lane forms the same sums in
+// the same order, so the result does not depend on scheduling).  One thread per element walking
+// all k was bound by the latency of its dependent loads.
 __global__ void __launch_bounds__(256) k_sum_splits(const float* partial, int nsplit, size_t n, float* grad)
 {
-    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= n) return;
+    const int l = threadIdx.x & 7;
+    const size_t e = size_t(blockIdx.x) * 32 + (threadIdx.x >> 3);
     float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += partial[size_t(k) * n + e];
-    grad[e] = s;
+    if (e < n)
+        for (int k = l; k < nsplit; k += 8) s += partial[size_t(k) * n + e];
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    if (e < n && l == 0) grad[e] = s;
 }
 
 // Bias gradient partials: part[b][co] = sum of dz[p][co] over the pixels p of chunk b (chunk pixels
@@ -417,15 +425,6 @@ __global__ void __launch_bounds__(256) k_bias_partial(CSlice dz, int P, int Cout
         }
         __syncthreads();
     }
-}
-
-__global__ void __launch_bounds__(256) k_bias_reduce(const float* part, int nb, int Cout, float* grad)
-{
-    const int co = blockIdx.x * 256 + threadIdx.x;
-    if (co >= Cout) return;
-    float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[size_t(b) * Cout + co];
-    grad[co] = s;
 }
 
 // Kernel for the input gradient: wt[tap][ci][co] = w[taps - 1 - tap][co][ci] (mirrored taps,
@@ -848,11 +847,12 @@ hipError_t conv_wgrad(CSlice x, CSlice dz, float* dw, float* db, float* work, in
         hipLaunchKernelGGL(k_conv_wgrad<9>, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(pl.per)), dim3(256), 0, st, work, pl.nsplit, pl.per, dw);
+    hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((pl.per + 31) / 32)), dim3(256), 0, st, work, pl.nsplit, pl.per, dw);
     if (db) {
         float* bpart = work + size_t(pl.nsplit) * pl.per;
         hipLaunchKernelGGL(k_bias_partial, dim3(pl.nb), dim3(256), 0, st, dz, P, Cout, pl.bchunk, bpart);
-        hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(size_t(Cout))), dim3(256), 0, st, bpart, pl.nb, Cout, db);
+        hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((Cout + 31) / 32)), dim3(256), 0, st, bpart, pl.nb,
+                           size_t(Cout), db);
     }
     return hipGetLastError();
 }
