@@ -302,65 +302,123 @@ struct WgradArgs {
     CSlice x;        // layer input, Cin channels
     CSlice dz;       // output gradient, Cout channels
     float* partial;  // [nsplit][taps][Cout][Cin]
-    int N, H, W, Cin, Cout, chunk;  // chunk: pixels per split (multiple of TK)
+    int N, H, W, Cin, Cout, chunk;  // chunk: pixels per split (a multiple of 64)
     int periodic;
 };
 
 // partial[s][tap][co][ci] = sum over the pixels p of split s of dz[p][co] x[p + off(tap)][ci].
-// GEMM with M = Cout, N = Cin, K = pixels; both operands are staged through LDS transposed to
-// K-contiguous rows.  Grid (Cout / 64, Cin / 64, taps * nsplit).
+// GEMM with M = Cout, N = Cin, K = pixels, in steps of TKW = 64 pixels (two 32-deep MFMA steps per
+// barrier); grid (Cout / 64, Cin / 64, taps * nsplit), four waves each with a 32 x 32 part.  Both
+// operands are transposed to pixel-contiguous LDS rows (row = channel): thread t loads, per step,
+// the 8-channel group t % 8 of the pixel pair 2 (t / 8) .. +1 for both operands (16-byte loads, eight
+// consecutive lanes covering one pixel's 64 channels) and writes each channel's two pixels as one
+// 32-bit word.  Pixel k of row r sits in column (k + 8 sw(r)) mod 64, sw(r) = (r ^ (r >> 3)) & 7:
+// the eight lanes of a pixel pair (rows 8 g + e) and the sixteen rows an MFMA operand read spans
+// then fall in different banks, while each 8-pixel group stays one aligned 16-byte read.  The next
+// step's operands are loaded into registers while the current step is multiplied, LDS is
+// double-buffered (one barrier per step), and the pixel coordinates advance incrementally.
+constexpr int TKW = 64;
+
+__device__ __forceinline__ int wg_col(int r, int k) { return (k + 8 * ((r ^ (r >> 3)) & 7)) & (TKW - 1); }
+
 template <int TAPS>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const WgradArgs a)
 {
-    __shared__ __align__(16) bf16 As[TM * LDK];
-    __shared__ __align__(16) bf16 Bs[TN * LDK];
+    __shared__ __align__(16) bf16 As[2][TM * TKW];
+    __shared__ __align__(16) bf16 Bs[2][TN * TKW];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int P = a.N * a.H * a.W;
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
     const int tap = blockIdx.z % TAPS, split = blockIdx.z / TAPS;
     const int dy = (TAPS == 9 ? tap / 3 - 1 : 0), dx = (TAPS == 9 ? tap % 3 - 1 : 0);
     const int pbeg = split * a.chunk, pend = min(P, pbeg + a.chunk);
-    const int lp = tid / 8, lc = (tid % 8) * 8;  // pixel of the K tile, 8-channel group
+    const int pp = tid / 8, cg = tid % 8;  // pixel pair of the step, 8-channel group
+    const bool a_ok = m0 + 8 * cg < a.Cout, b_ok = n0 + 8 * cg < a.Cin;
+    // coordinates of this thread's first pixel of the current step, advanced by TKW per step
+    int p = pbeg + 2 * pp, pn = 0, py = 0, px = 0;
+    if (p < P) decompose(p, a.H, a.W, pn, py, px);
+    bf16x8 ra[2], rb[2];
+    auto load = [&]() __attribute__((always_inline)) {
+        int n = pn, y = py, x = px;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            ra[h] = bf16x8{};
+            rb[h] = bf16x8{};
+            if (p + h < pend) {
+                if (a_ok) ra[h] = *reinterpret_cast<const bf16x8*>(a.dz.p + size_t(p + h) * a.dz.cs + a.dz.co + m0 + 8 * cg);
+                int yy = y + dy, xx = x + dx;
+                if (a.periodic) {
+                    yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+                    xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+                }
+                if (b_ok && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    rb[h] = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((n * a.H + yy) * a.W + xx) * a.x.cs + a.x.co +
+                                                             n0 + 8 * cg);
+            }
+            if (++x == a.W) {  // the pair's second pixel
+                x = 0;
+                if (++y == a.H) {
+                    y = 0;
+                    ++n;
+                }
+            }
+        }
+        // advance to the next step: TKW pixels further
+        p += TKW;
+        px += TKW;
+        while (px >= a.W) {
+            px -= a.W;
+            if (++py == a.H) {
+                py = 0;
+                ++pn;
+            }
+        }
+    };
+    auto stash = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int r = 8 * cg + e;
+            const int c = wg_col(r, 2 * pp);
+            const __attribute__((ext_vector_type(2))) __bf16 wa = {ra[0][e], ra[1][e]};
+            const __attribute__((ext_vector_type(2))) __bf16 wb = {rb[0][e], rb[1][e]};
+            *reinterpret_cast<__attribute__((ext_vector_type(2))) __bf16*>(&As[buf][r * TKW + c]) = wa;
+            *reinterpret_cast<__attribute__((ext_vector_type(2))) __bf16*>(&Bs[buf][r * TKW + c]) = wb;
+        }
+    };
     f4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
-    for (int k0 = pbeg; k0 < pend; k0 += TK) {
-        const int p = k0 + lp;
-        bf16x8 va = {}, vb = {};
-        if (p < pend) {
-            if (m0 + lc < a.Cout)
-                va = *reinterpret_cast<const bf16x8*>(a.dz.p + size_t(p) * a.dz.cs + a.dz.co + m0 + lc);
-            int pn, py, px;
-            decompose(p, a.H, a.W, pn, py, px);
-            int yy = py + dy, xx = px + dx;
-            if (a.periodic) {
-                yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
-                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
-            }
-            if (n0 + lc < a.Cin && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                vb = *reinterpret_cast<const bf16x8*>(a.x.p + size_t((pn * a.H + yy) * a.W + xx) * a.x.cs + a.x.co +
-                                                      n0 + lc);
-        }
+    load();
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = pbeg; k0 < pend; k0 += TKW) {
+        const bool more = k0 + TKW < pend;
+        if (more) load();
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            As[(lc + e) * LDK + lp] = va[e];
-            Bs[(lc + e) * LDK + lp] = vb[e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + lane % 16) * LDK + 8 * (lane / 16));
+        for (int h = 0; h < TKW / 32; ++h) {
+            const int k = 32 * h + 8 * (lane / 16);
+            bf16x8 fb[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const bf16x8 fb =
-                    *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + lane % 16) * LDK + 8 * (lane / 16));
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i][j], 0, 0, 0);
+                const int r = wn + 16 * j + lane % 16;
+                fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][r * TKW + wg_col(r, k)]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm + 16 * i + lane % 16;
+                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&As[buf][r * TKW + wg_col(r, k)]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
             }
         }
+        if (more) stash(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
     float* out = a.partial + (size_t(split) * TAPS + tap) * size_t(a.Cout) * a.Cin;
 #pragma unroll
@@ -377,7 +435,6 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const WgradArgs a)
         }
 }
 
-// grad[e] = sum_s partial[s][e], in split order (deterministic).
 // grad[e] = sum over k < nsplit of partial[k][e]: 32 elements per block, eight lanes per element
 // summing interleaved k, then a butterfly over the eight lanes (every lane forms the same sums in
 // the same order, so the result does not depend on scheduling).  One thread per element walking
@@ -827,7 +884,7 @@ WgradPlan wgrad_plan(int P, int Cin, int Cout, int taps)
     WgradPlan w{};
     const int tiles = taps * ((Cout + TM - 1) / TM) * ((Cin + TN - 1) / TN);
     const int target = std::max(1, std::min(1024 / tiles, P / 256));
-    w.chunk = ((P + target - 1) / target + TK - 1) / TK * TK;
+    w.chunk = ((P + target - 1) / target + TKW - 1) / TKW * TKW;
     w.nsplit = std::max(1, (P + w.chunk - 1) / w.chunk);
     w.nb = std::min(256, (P + 255) / 256);  // bias partials: at most 256 pixel chunks
     w.bchunk = (P + w.nb - 1) / w.nb;
