@@ -36,7 +36,7 @@ typedef __attribute__((ext_vector_type(4))) float f4;
 
 // ------------------------------------------------------------------------ matrix-core GEMMs
 
-constexpr int TM = 64, TN = 64, TK = 32, LDK = 40;  // LDS rows padded to 40 bf16 (80 bytes)
+constexpr int TM = 64, TN = 64, TK = 32;
 
 // A channel slice of an NHWC bf16 tensor: element (pixel p, channel c) at p * cs + co + c.
 struct Slice {
@@ -68,9 +68,12 @@ __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, i
     x = r - y * W;
 }
 
-// 16 zero bytes: the source of the operand chunks that lie outside the image (zero padding), past
-// the end of K or past the last pixel or output channel, for the direct-to-LDS loads below.
-__device__ __align__(16) uint4 g_zero16 = {0u, 0u, 0u, 0u};
+// Zeros: the source of the operand chunks that lie outside the image (zero padding), past the end
+// of K or past the last pixel or output channel, for the direct-to-LDS loads below.  Such a chunk's
+// address is this buffer plus the chunk's channel offset, so it must hold the widest input (the
+// largest concatenation the network configuration allows is 12288 channels).
+constexpr int kZeroElems = 12288 + 64;
+__device__ __align__(16) bf16 g_zero[kZeroElems] = {};
 
 // LDS slot of 16-byte K group q of operand row r in a stage: rows of four groups (64 bytes), the
 // group index XOR-swizzled by row so that the 16-byte reads of the MFMA operands (16 consecutive
@@ -120,16 +123,15 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
     }
     const int co = n0 + tid / 4;
     const bool b_loader = tid < BT;  // wave-uniform (BT is a multiple of 64)
-    const bf16* zero = reinterpret_cast<const bf16*>(&g_zero16);
-
-    // The K position of this thread's group walks forward by TK per step: (tap, ci) and the element
-    // offsets of the operand rows for the current tap are updated incrementally (no division per
-    // step); they change tap only every Cin / TK steps.
-    int kc = kb + q * 8;
-    int tap = kc / a.Cin, ci = kc - tap * a.Cin;
-    long aoff[AJ];
-    bool aval[AJ];
-    long boff = 0;
+    // The K position of this thread's group walks forward by TK per step.  Each operand row has a
+    // base pointer for the current tap (into the zero buffer where the row lies outside the image or
+    // the tap is past the last one, which also covers the end of K), and a step's chunk is that base
+    // plus the channel offset ci; (tap, ci) advance by adds, and the bases change only every Cin / TK
+    // steps.  A division or a bounds test per step made the kernel bound by vector issue.
+    int tap = (kb + q * 8) / a.Cin, ci = kb + q * 8 - tap * a.Cin;
+    const bf16* zero = g_zero;  // (the lambdas below take the pointer, not the device variable)
+    const bf16* abase[AJ];
+    const bf16* bbase = zero;
     auto set_tap = [&](int t) __attribute__((always_inline)) {
         const int dy = (TAPS == 9 ? t / 3 - 1 : 0), dx = (TAPS == 9 ? t % 3 - 1 : 0);
 #pragma unroll
@@ -139,37 +141,37 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
                 yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
                 xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
             }
-            aval[j] = pin[j] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-            aoff[j] = long((pn[j] * a.H + yy) * a.W + xx) * a.x.cs + a.x.co;
+            const bool in = t < TAPS && pin[j] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            abase[j] = in ? a.x.p + long((pn[j] * a.H + yy) * a.W + xx) * a.x.cs + a.x.co : zero;
         }
-        boff = long(t * a.Cout + co) * a.Cin;
+        bbase = (t < TAPS && co < a.Cout) ? a.w + long(t * a.Cout + co) * a.Cin : zero;
     };
-    set_tap(tap < TAPS ? tap : 0);
+    set_tap(tap);
 
     auto issue = [&](int step) __attribute__((always_inline)) {
         const int stage = step % NS;
-        const bool kin = kc < K;
 #pragma unroll
+        // (the addresses go through named locals: with the sum written as the builtin's argument
+        // the host pass drops the kernel's instantiation without a diagnostic)
         for (int j = 0; j < AJ; ++j) {
-            const bf16* src = (kin && aval[j]) ? a.x.p + aoff[j] + ci : zero;
+            const bf16* src = abase[j] + ci;
             __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(As + stage * BM * 32 +
                                                                                               (256 * j + wave * 64) * 8),
                                              16, 0, 0);
         }
         if (b_loader) {
-            const bf16* src = (kin && co < a.Cout) ? a.w + boff + ci : zero;
+            const bf16* src = bbase + ci;
             __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(Bs + stage * BN * 32 +
                                                                                               wave * 64 * 8),
                                              16, 0, 0);
         }
-        kc += TK;
         ci += TK;
         if (ci >= a.Cin) {
             do {
                 ci -= a.Cin;
                 ++tap;
             } while (ci >= a.Cin);
-            if (tap < TAPS) set_tap(tap);
+            set_tap(tap);
         }
     };
 
@@ -820,6 +822,7 @@ size_t fwd_split_elems(long P, int Cin, int Cout, int taps)
 hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
                         int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems)
 {
+    if (Cin + 8 > kZeroElems || Cin % 8 || Cout < 1) return hipErrorInvalidValue;
     ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0};
     const long P = long(N) * H * W;
     // split K over a workspace when the grid alone cannot fill the chip

@@ -218,3 +218,14 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_library_defines_every_kernel_it_launches():
+    """Every kernel handle the host code references is defined in the library (a template kernel
+    whose host-side instantiation was dropped shows up as an undefined symbol, and loading fails
+    only at the first launch of that kernel)."""
+    import subprocess
+    from paper_2012_14707_amd import build as B
+    out = subprocess.run(["nm", "-D", "--undefined-only", B.LIB], capture_output=True, text=True, check=True).stdout
+    undefined = [line.split()[-1] for line in out.splitlines() if line.strip()]
+    assert not [s for s in undefined if s.startswith("_ZN3lbm")], undefined
