@@ -284,6 +284,184 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
         }
 }
 
+// LDS slot of 16-byte K group q of row r in the halo-tile kernel below: any 16 consecutive rows
+// (one MFMA operand read, which starts at any pixel shift) fall in distinct banks.
+__device__ __forceinline__ int tile_slot(int r, int q) { return r * 4 + (q ^ ((r >> 2) & 3)); }
+
+// 3x3 convolution on spatial tiles (same result as k_conv_fwd<9, ...>, with a.kper in channels).
+// A block computes TH x TW output pixels of one image (H and W multiples of the tile) and BN output
+// channels.  K runs over 32-channel chunks of the input; per chunk, the block stages the input
+// halo tile ((TH + 2) x (TW + 2) pixels, periodic or zero edges) and the weights of all nine taps
+// in LDS, then every tap reads its operand as a shifted window of the halo tile.  The input is thus
+// read once per chunk instead of once per tap, and each wave does 9 RW (TW / 16) (CW / 16) MFMAs
+// per barrier: the K step of the pixel-row kernel above gives 4-8, too few to cover the load
+// latency and the barrier.  Waves form a WR x (4 / WR) grid over tile rows x output channels; a
+// wave reads each halo-row window once and applies it to up to three of its output rows.  NS
+// stages (2: the next chunk's direct loads are issued right after the barrier; 1: single chunk).
+// Thread t fills the 16-byte slots 256 j + t of each stage (the lane order of its wave's direct
+// loads); a slot's row and swizzled K group fix the source address, which is set once and then
+// advanced by the chunk offset.
+template <int TH, int TW, int BN, int WR, int NS>
+__global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
+{
+    constexpr int WC = 4 / WR, RW = TH / WR, CW = BN / WC, CG = TW / 16, NJ = CW / 16;
+    constexpr int HW = TW + 2, HP = (TH + 2) * HW;
+    constexpr int JA = (4 * HP + 255) / 256, JB = (36 * BN + 255) / 256;
+    constexpr int SA = JA * 256, SS = SA + JB * 256;  // 16-byte slots: input part, one stage
+    static_assert(WR * WC == 4 && RW * WR == TH && CW * WC == BN && NJ * 16 == CW && CG * 16 == TW, "tile shape");
+    static_assert(NS == 1 || NS == 2, "one or two stages");
+    __shared__ __align__(16) bf16x8 lds[NS * SS];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int tiles_x = a.W / TW, tiles_y = a.H / TH;
+    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, n = blockIdx.x / (tiles_x * tiles_y);
+    const int y0 = ty * TH, x0 = tx * TW, n0 = blockIdx.y * BN;
+    const int c_begin = a.part ? blockIdx.z * a.kper : 0;
+    const int c_end = a.part ? min(a.Cin, c_begin + a.kper) : a.Cin;
+    const int nsteps = (c_end - c_begin + TK - 1) / TK;
+    // slot 256 j + t holds row (256 j + t) / 4 and K group q (the same q for every j)
+    const int q8 = 8 * ((tid & 3) ^ ((tid >> 4) & 3));
+    const bf16* zero = g_zero;
+    const bf16* asrc[JA];
+    const bf16* bsrc[JB];
+#pragma unroll
+    for (int j = 0; j < JA; ++j) {
+        const int r = (256 * j + tid) >> 2;
+        const int hy = r / HW, hx = r - hy * HW;
+        int yy = y0 - 1 + hy, xx = x0 - 1 + hx;
+        if (a.periodic) {
+            yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+            xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+        }
+        const bool in = r < HP && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        asrc[j] = (in ? a.x.p + long((n * a.H + yy) * a.W + xx) * a.x.cs + a.x.co : zero) + q8;
+    }
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        const int r = (256 * j + tid) >> 2;
+        const int t = r / BN, co = n0 + r - t * BN;
+        const bool in = t < 9 && co < a.Cout;
+        bsrc[j] = (in ? a.w + long(t * a.Cout + co) * a.Cin : zero) + q8;
+    }
+
+    auto issue = [&](int step) __attribute__((always_inline)) {
+        bf16x8* A = lds + (step % NS) * SS;
+        const int c = c_begin + step * TK;
+        const bool ok = c + q8 < c_end;  // past the chunk's end: zeros
+#pragma unroll
+        for (int j = 0; j < JA; ++j) {
+            const bf16* src = ok ? asrc[j] + c : zero;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + 256 * j + 64 * wave), 16,
+                                             0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            const bf16* src = ok ? bsrc[j] + c : zero;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + SA + 256 * j + 64 * wave),
+                                             16, 0, 0);
+        }
+    };
+
+    const int wr = wave / WC, wc = wave % WC;
+    f4 acc[RW][CG][NJ];
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int g = 0; g < CG; ++g)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[i][g][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    issue(0);
+    for (int s = 0; s < nsteps; ++s) {
+        // this thread's loads of chunk s have landed (the next chunk's are issued below); the
+        // barrier makes every thread's visible and frees the other stage (its chunk is done)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (NS == 2 && s + 1 < nsteps) issue(s + 1);
+        const bf16x8* A = lds + (s % NS) * SS;
+        const bf16x8* B = A + SA;
+        bf16x8 fb[9][NJ];
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) fb[t][j] = B[tile_slot(t * BN + wc * CW + 16 * j + lane % 16, lane / 16)];
+        // halo row h of this wave (tile row wr RW + h - 1) feeds output row i through tap row h - i
+#pragma unroll
+        for (int h = 0; h < RW + 2; ++h)
+#pragma unroll
+            for (int g = 0; g < CG; ++g)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const bf16x8 fa = A[tile_slot((wr * RW + h) * HW + 16 * g + dx + lane % 16, lane / 16)];
+#pragma unroll
+                    for (int i = 0; i < RW; ++i) {
+                        if (h - i < 0 || h - i > 2) continue;
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j)
+                            acc[i][g][j] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[(h - i) * 3 + dx][j], acc[i][g][j], 0, 0, 0);
+                    }
+                }
+        asm volatile("" ::: "memory");
+    }
+
+    // lane holds output channel lane % 16 of each 16-channel group and pixels 4 (lane / 16) + r of
+    // each 16-pixel group
+    auto pixel = [&](int i, int g, int r) __attribute__((always_inline)) {
+        return size_t(n * a.H + y0 + wr * RW + i) * a.W + x0 + 16 * g + 4 * (lane / 16) + r;
+    };
+    if (a.part) {
+        float* out = a.part + size_t(blockIdx.z) * size_t(a.N) * a.H * a.W * a.Cout;
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int g = 0; g < CG; ++g)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const int col = n0 + wc * CW + 16 * j + lane % 16;
+                    if (col >= a.Cout) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[pixel(i, g, r) * a.Cout + col] = acc[i][g][j][r];
+                }
+        return;
+    }
+    const bool staged = a.y.p && a.Cout % 8 == 0 && a.y.cs % 8 == 0 && a.y.co % 8 == 0;
+    constexpr int BNP = BN + 8;  // padded LDS row of the staged output tile
+    static_assert(TH * TW * BNP * 2 <= NS * SS * 16, "the output tile fits the operand stages");
+    bf16* Cs = reinterpret_cast<bf16*>(lds);
+    if (staged) __syncthreads();  // every wave is done with the operand stages
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int g = 0; g < CG; ++g)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int cl = wc * CW + 16 * j + lane % 16, col = n0 + cl;
+                if (col >= a.Cout) continue;
+                const float b = a.bias ? a.bias[col] : 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[i][g][j][r] + b;
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    if (a.yf) a.yf[pixel(i, g, r) * a.Cout + col] = v;
+                    if (staged)
+                        Cs[((wr * RW + i) * TW + 16 * g + 4 * (lane / 16) + r) * BNP + cl] = bf16(v);
+                    else if (a.y.p)
+                        a.y.p[pixel(i, g, r) * a.y.cs + a.y.co + col] = bf16(v);
+                }
+            }
+    if (!staged) return;
+    __syncthreads();
+    constexpr int G = BN / 8;  // 8-channel chunks per tile pixel
+    for (int c = tid; c < TH * TW * G; c += 256) {
+        const int p = c / G, col = n0 + 8 * (c % G);
+        if (col >= a.Cout) continue;
+        const size_t px = size_t(n * a.H + y0 + p / TW) * a.W + x0 + p % TW;
+        *reinterpret_cast<bf16x8*>(a.y.p + px * a.y.cs + a.y.co + col) =
+            *reinterpret_cast<const bf16x8*>(Cs + p * BNP + 8 * (c % G));
+    }
+}
+
 __global__ void __launch_bounds__(256) k_split_sum(const ConvArgs a, int splits)
 {
     const size_t P = size_t(a.N) * a.H * a.W;
@@ -798,12 +976,13 @@ inline unsigned blocks(size_t n) { return unsigned((n + 255) / 256); }
 
 // ------------------------------------------------------------------------------- launchers
 
-// Splits of the K range for a convolution whose 64 x 64 grid has too few blocks to fill the chip:
-// enough splits for about 1024 blocks, at most 8, each at least 16 K steps long (1 = no split).
-// pipeline stages of the convolution kernel (3 measured faster than 2 or 4)
+// pipeline stages of the pixel-row convolution kernel (3 measured faster than 2 or 4)
 constexpr int kConvStages = 3;
 
-int fwd_splits(long P, int Cin, int Cout, int taps)
+// Splits of the K range for a pixel-row convolution whose 64 x 64 grid has too few blocks to fill
+// the chip: enough splits for about 1024 blocks, at most 8, each at least 16 K steps long (1 = no
+// split).
+int row_splits(long P, int Cin, int Cout, int taps)
 {
     const long tiles = ((P + 63) / 64) * ((Cout + 63) / 64);
     if (Cout < 64 || tiles >= 1024) return 1;
@@ -813,10 +992,65 @@ int fwd_splits(long P, int Cin, int Cout, int taps)
     return std::max(1, s);
 }
 
-size_t fwd_split_elems(long P, int Cin, int Cout, int taps)
+// Kernel and K split of one forward convolution.  3x3 convolutions whose image is a whole number
+// of tiles take the halo-tile kernel: 8 x 32 pixels x 64 channels when the output channels are a
+// multiple of 64 and that still gives a block per compute unit (256), else 8 x 16 x 64, else
+// 16 x 32 x 32; K is split (over the workspace) when the grid has fewer than 256 blocks, at most 8
+// ways and, with four or more chunks, at least two 32-channel chunks per split.
+struct FwdPlan {
+    int kind;    // 0: pixel-row kernel; 1: tiles 16 x 32 x 32; 2: 8 x 32 x 64; 3: 8 x 16 x 64
+    int splits;  // K splits, 1: none
+    int kper;    // K per split: input channels (tiles) or (tap, channel) positions (pixel rows)
+};
+
+FwdPlan fwd_plan(int N, int H, int W, int Cin, int Cout, int taps)
 {
-    const int s = fwd_splits(P, Cin, Cout, taps);
-    return s > 1 ? size_t(s) * size_t(P) * size_t(Cout) : 0;
+    FwdPlan f{0, 1, 0};
+    const long P = long(N) * H * W;
+    if (taps == 9 && Cin + 32 <= kZeroElems) {
+        auto nb = [&](int th, int tw, int bn) { return long(N) * (H / th) * (W / tw) * ((Cout + bn - 1) / bn); };
+        long blocks = 0;
+        if (Cout % 64 == 0 && H % 8 == 0 && W % 32 == 0 && nb(8, 32, 64) >= 256) {
+            f.kind = 2;
+            blocks = nb(8, 32, 64);
+        } else if (Cout % 64 == 0 && H % 8 == 0 && W % 16 == 0) {
+            f.kind = 3;
+            blocks = nb(8, 16, 64);
+        } else if (H % 16 == 0 && W % 32 == 0) {
+            f.kind = 1;
+            blocks = nb(16, 32, 32);
+        }
+        if (f.kind) {
+            const int chunks = (Cin + TK - 1) / TK;
+            int s = blocks >= 256 ? 1 : int(std::min<long>({8, (256 + blocks - 1) / blocks, long(chunks)}));
+            if (chunks >= 4) s = std::min(s, chunks / 2);
+            s = std::max(s, 1);
+            f.kper = (chunks + s - 1) / s * TK;
+            f.splits = (Cin + f.kper - 1) / f.kper;
+            return f;
+        }
+    }
+    f.splits = row_splits(P, Cin, Cout, taps);
+    const int K = taps * Cin;
+    f.kper = ((K + f.splits - 1) / f.splits + TK - 1) / TK * TK;
+    f.splits = (K + f.kper - 1) / f.kper;
+    return f;
+}
+
+size_t fwd_split_elems(int N, int H, int W, int Cin, int Cout, int taps)
+{
+    const FwdPlan f = fwd_plan(N, H, W, Cin, Cout, taps);
+    return f.splits > 1 ? size_t(f.splits) * size_t(N) * H * W * size_t(Cout) : 0;
+}
+
+template <int TH, int TW, int BN, int WR>
+void launch_tile(const ConvArgs& a, int nsplit, int chunks_per_block, hipStream_t st)
+{
+    const dim3 grid(unsigned(a.N * (a.H / TH) * (a.W / TW)), unsigned((a.Cout + BN - 1) / BN), unsigned(nsplit));
+    if (chunks_per_block > 1)
+        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 2>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 1>), grid, dim3(256), 0, st, a);
 }
 
 hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
@@ -825,13 +1059,23 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
     if (Cin + 8 > kZeroElems || Cin % 8 || Cout < 1) return hipErrorInvalidValue;
     ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0};
     const long P = long(N) * H * W;
-    // split K over a workspace when the grid alone cannot fill the chip
-    const int splits = fwd_splits(P, Cin, Cout, taps);
-    if (splits > 1 && ws && ws_elems >= fwd_split_elems(P, Cin, Cout, taps)) {
-        const int K = taps * Cin;
+    const FwdPlan f = fwd_plan(N, H, W, Cin, Cout, taps);
+    // split K over the workspace when the plan asks for it and the workspace holds the partials
+    const bool split = f.splits > 1 && ws && ws_elems >= fwd_split_elems(N, H, W, Cin, Cout, taps);
+    if (split) {
         a.part = ws;
-        a.kper = ((K + splits - 1) / splits + TK - 1) / TK * TK;
-        const int nsplit = (K + a.kper - 1) / a.kper;
+        a.kper = f.kper;
+    }
+    const int nsplit = split ? f.splits : 1;
+    if (f.kind) {
+        const int chunks = ((split ? f.kper : Cin) + TK - 1) / TK;
+        if (f.kind == 1) launch_tile<16, 32, 32, 4>(a, nsplit, chunks, st);
+        else if (f.kind == 2) launch_tile<8, 32, 64, 2>(a, nsplit, chunks, st);
+        else launch_tile<8, 16, 64, 2>(a, nsplit, chunks, st);
+        if (split) hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
+        return hipGetLastError();
+    }
+    if (split) {
         const dim3 grid(unsigned((P + 63) / 64), unsigned((Cout + 63) / 64), unsigned(nsplit));
         const size_t lds = size_t(kConvStages) * (64 + 64) * 64;
         if (taps == 9)
@@ -842,17 +1086,17 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         return hipGetLastError();
     }
     // the largest tile that still leaves about four blocks per compute unit (256 CUs)
-    auto blocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
+    auto nblocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
     auto go = [&](auto kern, int bm, int bn) {
         const dim3 grid(unsigned((P + bm - 1) / bm), unsigned((Cout + bn - 1) / bn));
         hipLaunchKernelGGL(kern, grid, dim3(256), size_t(kConvStages) * (bm + bn) * 64, st, a);
     };
     const bool t9 = taps == 9;
-    if (Cout >= 64 && blocks(128, 64) >= 1024)
+    if (Cout >= 64 && nblocks(128, 64) >= 1024)
         t9 ? go(k_conv_fwd<9, 128, 64, kConvStages>, 128, 64) : go(k_conv_fwd<1, 128, 64, kConvStages>, 128, 64);
     else if (Cout >= 64)
         t9 ? go(k_conv_fwd<9, 64, 64, kConvStages>, 64, 64) : go(k_conv_fwd<1, 64, 64, kConvStages>, 64, 64);
-    else if (blocks(128, 32) >= 1024)
+    else if (nblocks(128, 32) >= 1024)
         t9 ? go(k_conv_fwd<9, 128, 32, kConvStages>, 128, 32) : go(k_conv_fwd<1, 128, 32, kConvStages>, 128, 32);
     else
         t9 ? go(k_conv_fwd<9, 64, 32, kConvStages>, 64, 32) : go(k_conv_fwd<1, 64, 32, kConvStages>, 64, 32);
@@ -1253,8 +1497,12 @@ lbm_status lbm_nn_create(const lbm_nn_config* cfg, uint64_t seed, void* stream, 
         const int P = int(B) * n->lv[cv->level].H * n->lv[cv->level].W;
         work = std::max(work, lbm::nn::wgrad_plan(P, cv->cin, cv->cout, cv->taps).elems);
         // split-K partial sums of the forward and of the input gradient (channel roles exchanged)
-        work = std::max(work, lbm::nn::fwd_split_elems(P, cv->cin, cv->cout, cv->taps));
-        work = std::max(work, lbm::nn::fwd_split_elems(P, cv->cout, cv->cin, cv->taps));
+        // (for every batch size up to the maximum: smaller batches split more ways)
+        const int lh = n->lv[cv->level].H, lw = n->lv[cv->level].W;
+        for (int nb = 1; nb <= int(B); ++nb) {
+            work = std::max(work, lbm::nn::fwd_split_elems(nb, lh, lw, cv->cin, cv->cout, cv->taps));
+            work = std::max(work, lbm::nn::fwd_split_elems(nb, lh, lw, cv->cout, cv->cin, cv->taps));
+        }
     }
     n->work_elems = work;
     const size_t px0 = B * c.height * c.width;

@@ -57,6 +57,12 @@ CONV_CASES = [
     (2, 16, 16, 512, 64, 3),
     (2, 19, 11, 96, 32, 1),
     (1, 32, 32, 32, 8, 1),
+    # 3x3 halo tiles: 16 x 32 x 32 with one chunk, with a short last chunk and three channel tiles;
+    # 8 x 16 x 64 with a short single chunk; 8 x 32 x 64 (enough blocks at batch 4)
+    (2, 32, 64, 32, 32, 3),
+    (1, 16, 32, 48, 96, 3),
+    (2, 16, 64, 16, 64, 3),
+    (4, 128, 128, 32, 64, 3),
 ]
 
 
