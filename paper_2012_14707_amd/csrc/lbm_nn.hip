@@ -284,9 +284,103 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const ConvArgs a)
         }
 }
 
-// LDS slot of 16-byte K group q of row r in the halo-tile kernel below: any 16 consecutive rows
-// (one MFMA operand read, which starts at any pixel shift) fall in distinct banks.
-__device__ __forceinline__ int tile_slot(int r, int q) { return r * 4 + (q ^ ((r >> 2) & 3)); }
+// LDS rows of the halo-tile kernel: a row (one pixel's or one output channel's 32-channel chunk,
+// four 16-byte K groups) takes five 16-byte slots.  The 80-byte stride puts the 16-byte reads of any
+// 16 consecutive rows (one MFMA operand, which starts at any pixel shift) in distinct banks, and a
+// read's address is a per-lane base plus a constant.
+constexpr int kTileRow = 5;
+
+// Output of a halo tile (k_conv_tile).  Lane (wave row wr, wave channel group wc)
+// holds, for fragment (i, g, j), output channel n0 + wc CW + 16 j + lane % 16 of the pixels
+// 4 (lane / 16) + r, r < 4, of tile row wr RW + i, columns 16 g + ...: each lane computes one
+// base address, and the offsets of its elements are uniform products (scalar arithmetic).  bf16
+// outputs go through LDS (the operand stages, free once every wave is past its last multiply) and
+// leave in 16-byte row chunks; fp32 outputs and split partials are stored from the registers.
+template <int TH, int TW, int BN, int WR, int LDSB, int RW = TH / WR, int CG = TW / 16, int NJ = BN / (4 / WR) / 16>
+__device__ __forceinline__ void tile_epilogue(const ConvArgs& a, const f4 (&acc)[RW][CG][NJ], bf16x8* lds,
+                                              int n, int y0, int x0, int n0, int wr, int wc, int lane, int tid)
+{
+    constexpr int CW = 16 * NJ;
+    const size_t W = size_t(a.W), Cout = size_t(a.Cout);
+    const int cl0 = wc * CW + lane % 16;
+    const size_t pix0 = (size_t(n) * a.H + y0 + wr * RW) * W + x0 + 4 * (lane / 16);
+    // pixel of element (i, g, r) = pix0 + off(i, g, r)
+    auto off = [&](int i, int g, int r) __attribute__((always_inline)) { return size_t(i) * W + 16 * g + r; };
+    if (a.part) {
+        float* out = a.part + (size_t(blockIdx.z) * a.N * a.H * W + pix0) * Cout + n0 + cl0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (n0 + cl0 + 16 * j >= a.Cout) continue;
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int g = 0; g < CG; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[off(i, g, r) * Cout + 16 * j] = acc[i][g][j][r];
+        }
+        return;
+    }
+    float bias[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int col = n0 + cl0 + 16 * j;
+        bias[j] = (a.bias && col < a.Cout) ? a.bias[col] : 0.f;
+    }
+    auto act = [&](float v) __attribute__((always_inline)) { return a.relu ? fmaxf(v, 0.f) : v; };
+    if (a.yf) {
+        float* out = a.yf + pix0 * Cout + n0 + cl0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (n0 + cl0 + 16 * j >= a.Cout) continue;
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int g = 0; g < CG; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[off(i, g, r) * Cout + 16 * j] = act(acc[i][g][j][r] + bias[j]);
+        }
+    }
+    if (!a.y.p) return;
+    const size_t cs = size_t(a.y.cs);
+    if (a.Cout % 8 || a.y.cs % 8 || a.y.co % 8) {
+        bf16* out = a.y.p + pix0 * cs + a.y.co + n0 + cl0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (n0 + cl0 + 16 * j >= a.Cout) continue;
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int g = 0; g < CG; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[off(i, g, r) * cs + 16 * j] = bf16(act(acc[i][g][j][r] + bias[j]));
+        }
+        return;
+    }
+    constexpr int BNP = BN + 8;  // padded LDS row of the staged tile
+    constexpr int G = BN / 8, PPI = 256 / G;  // 16-byte chunks per pixel, pixels per pass of the block
+    static_assert(PPI % TW == 0 && (TH * TW) % PPI == 0, "whole tile rows per pass");
+    static_assert(TH * TW * BNP * 2 <= LDSB, "the staged tile fits the operand stages");
+    bf16* Cs = reinterpret_cast<bf16*>(lds);
+    __syncthreads();  // every wave is done with the operand stages
+    bf16* cw = Cs + (wr * RW * TW + 4 * (lane / 16)) * BNP + cl0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int g = 0; g < CG; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cw[(i * TW + 16 * g + r) * BNP + 16 * j] = bf16(act(acc[i][g][j][r] + bias[j]));
+    __syncthreads();
+    const int p0 = tid / G, g8 = tid % G, col = n0 + 8 * g8;
+    if (col >= a.Cout) return;
+    const bf16* src = Cs + p0 * BNP + 8 * g8;
+    bf16* dst = a.y.p + ((size_t(n) * a.H + y0 + p0 / TW) * W + x0 + p0 % TW) * cs + a.y.co + col;
+#pragma unroll
+    for (int k = 0; k < TH * TW / PPI; ++k)
+        *reinterpret_cast<bf16x8*>(dst + size_t(k * (PPI / TW)) * W * cs) =
+            *reinterpret_cast<const bf16x8*>(src + k * PPI * BNP);
+}
 
 // 3x3 convolution on spatial tiles (same result as k_conv_fwd<9, ...>, with a.kper in channels).
 // A block computes TH x TW output pixels of one image (H and W multiples of the tile) and BN output
@@ -299,69 +393,89 @@ __device__ __forceinline__ int tile_slot(int r, int q) { return r * 4 + (q ^ ((r
 // wave reads each halo-row window once and applies it to up to three of its output rows.  NS
 // stages (2: the next chunk's direct loads are issued right after the barrier; 1: single chunk).
 // Thread t fills the 16-byte slots 256 j + t of each stage (the lane order of its wave's direct
-// loads); a slot's row and swizzled K group fix the source address, which is set once and then
-// advanced by the chunk offset.
+// loads); a slot's row and K group fix the source address, which is set once and then advanced
+// by the chunk offset (the fifth slot of a row, padding, loads zeros).
 template <int TH, int TW, int BN, int WR, int NS>
 __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
 {
     constexpr int WC = 4 / WR, RW = TH / WR, CW = BN / WC, CG = TW / 16, NJ = CW / 16;
     constexpr int HW = TW + 2, HP = (TH + 2) * HW;
-    constexpr int JA = (4 * HP + 255) / 256, JB = (36 * BN + 255) / 256;
+    constexpr int JA = (kTileRow * HP + 255) / 256, JB = (kTileRow * 9 * BN + 255) / 256;
     constexpr int SA = JA * 256, SS = SA + JB * 256;  // 16-byte slots: input part, one stage
     static_assert(WR * WC == 4 && RW * WR == TH && CW * WC == BN && NJ * 16 == CW && CG * 16 == TW, "tile shape");
     static_assert(NS == 1 || NS == 2, "one or two stages");
+    static_assert(NS * SS * 16 <= 163840, "LDS");
     __shared__ __align__(16) bf16x8 lds[NS * SS];
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int tid = threadIdx.x, lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int tiles_x = a.W / TW, tiles_y = a.H / TH;
     const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, n = blockIdx.x / (tiles_x * tiles_y);
     const int y0 = ty * TH, x0 = tx * TW, n0 = blockIdx.y * BN;
     const int c_begin = a.part ? blockIdx.z * a.kper : 0;
     const int c_end = a.part ? min(a.Cin, c_begin + a.kper) : a.Cin;
     const int nsteps = (c_end - c_begin + TK - 1) / TK;
-    // slot 256 j + t holds row (256 j + t) / 4 and K group q (the same q for every j)
-    const int q8 = 8 * ((tid & 3) ^ ((tid >> 4) & 3));
     const bf16* zero = g_zero;
+    // slot 256 j + t: row (256 j + t) / 5, K group (256 j + t) % 5 (4: padding)
     const bf16* asrc[JA];
     const bf16* bsrc[JB];
+    int aq8[JA], bq8[JB];
+    const unsigned img = unsigned(n) * unsigned(a.H) * unsigned(a.W);  // first pixel of image n
 #pragma unroll
     for (int j = 0; j < JA; ++j) {
-        const int r = (256 * j + tid) >> 2;
+        const int sl = 256 * j + tid, r = sl / kTileRow, q = sl - r * kTileRow;
         const int hy = r / HW, hx = r - hy * HW;
         int yy = y0 - 1 + hy, xx = x0 - 1 + hx;
         if (a.periodic) {
             yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
             xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
         }
-        const bool in = r < HP && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-        asrc[j] = (in ? a.x.p + long((n * a.H + yy) * a.W + xx) * a.x.cs + a.x.co : zero) + q8;
+        const bool in = q < 4 && r < HP && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        const unsigned pix = img + __umul24(unsigned(yy), unsigned(a.W)) + unsigned(xx);
+        aq8[j] = q < 4 ? 8 * q : 0;
+        asrc[j] = (in ? a.x.p + size_t(pix) * unsigned(a.x.cs) + a.x.co : zero) + aq8[j];
     }
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
-        const int r = (256 * j + tid) >> 2;
+        const int sl = 256 * j + tid, r = sl / kTileRow, q = sl - r * kTileRow;
         const int t = r / BN, co = n0 + r - t * BN;
-        const bool in = t < 9 && co < a.Cout;
-        bsrc[j] = (in ? a.w + long(t * a.Cout + co) * a.Cin : zero) + q8;
+        const bool in = q < 4 && t < 9 && co < a.Cout;
+        bq8[j] = q < 4 ? 8 * q : 0;
+        bsrc[j] = (in ? a.w + size_t(unsigned(t * a.Cout + co)) * unsigned(a.Cin) : zero) + bq8[j];
     }
 
     auto issue = [&](int step) __attribute__((always_inline)) {
-        bf16x8* A = lds + (step % NS) * SS;
+        bf16x8* A = lds + (step % NS) * SS + 64 * wave;
         const int c = c_begin + step * TK;
-        const bool ok = c + q8 < c_end;  // past the chunk's end: zeros
+        if (c + TK <= c_end) {
 #pragma unroll
-        for (int j = 0; j < JA; ++j) {
-            const bf16* src = ok ? asrc[j] + c : zero;
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + 256 * j + 64 * wave), 16,
-                                             0, 0);
-        }
+            for (int j = 0; j < JA; ++j) {
+                const bf16* src = asrc[j] + c;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + 256 * j), 16, 0, 0);
+            }
 #pragma unroll
-        for (int j = 0; j < JB; ++j) {
-            const bf16* src = ok ? bsrc[j] + c : zero;
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + SA + 256 * j + 64 * wave),
-                                             16, 0, 0);
+            for (int j = 0; j < JB; ++j) {
+                const bf16* src = bsrc[j] + c;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + SA + 256 * j), 16, 0, 0);
+            }
+        } else {  // a short last chunk: the groups past its end load zeros
+#pragma unroll
+            for (int j = 0; j < JA; ++j) {
+                const bf16* src = c + aq8[j] < c_end ? asrc[j] + c : zero;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + 256 * j), 16, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const bf16* src = c + bq8[j] < c_end ? bsrc[j] + c : zero;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(A + SA + 256 * j), 16, 0, 0);
+            }
         }
     };
 
     const int wr = wave / WC, wc = wave % WC;
+    // this lane's operand rows: halo row wr RW + h, column 16 g + dx + lane % 16 (group lane / 16);
+    // weight row t BN + wc CW + 16 j + lane % 16
+    const int a_lane = ((wr * RW) * HW + lane % 16) * kTileRow + lane / 16;
+    const int b_lane = SA + (wc * CW + lane % 16) * kTileRow + lane / 16;
     f4 acc[RW][CG][NJ];
 #pragma unroll
     for (int i = 0; i < RW; ++i)
@@ -378,13 +492,14 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
         if (NS == 2 && s + 1 < nsteps) issue(s + 1);
-        const bf16x8* A = lds + (s % NS) * SS;
-        const bf16x8* B = A + SA;
+        const bf16x8* St = lds + (s % NS) * SS;
+        const bf16x8* A = St + a_lane;
+        const bf16x8* B = St + b_lane;
         bf16x8 fb[9][NJ];
 #pragma unroll
         for (int t = 0; t < 9; ++t)
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) fb[t][j] = B[tile_slot(t * BN + wc * CW + 16 * j + lane % 16, lane / 16)];
+            for (int j = 0; j < NJ; ++j) fb[t][j] = B[(t * BN + 16 * j) * kTileRow];
         // halo row h of this wave (tile row wr RW + h - 1) feeds output row i through tap row h - i
 #pragma unroll
         for (int h = 0; h < RW + 2; ++h)
@@ -392,7 +507,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
             for (int g = 0; g < CG; ++g)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
-                    const bf16x8 fa = A[tile_slot((wr * RW + h) * HW + 16 * g + dx + lane % 16, lane / 16)];
+                    const bf16x8 fa = A[(h * HW + 16 * g + dx) * kTileRow];
 #pragma unroll
                     for (int i = 0; i < RW; ++i) {
                         if (h - i < 0 || h - i > 2) continue;
@@ -405,61 +520,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
         asm volatile("" ::: "memory");
     }
 
-    // lane holds output channel lane % 16 of each 16-channel group and pixels 4 (lane / 16) + r of
-    // each 16-pixel group
-    auto pixel = [&](int i, int g, int r) __attribute__((always_inline)) {
-        return size_t(n * a.H + y0 + wr * RW + i) * a.W + x0 + 16 * g + 4 * (lane / 16) + r;
-    };
-    if (a.part) {
-        float* out = a.part + size_t(blockIdx.z) * size_t(a.N) * a.H * a.W * a.Cout;
-#pragma unroll
-        for (int i = 0; i < RW; ++i)
-#pragma unroll
-            for (int g = 0; g < CG; ++g)
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) {
-                    const int col = n0 + wc * CW + 16 * j + lane % 16;
-                    if (col >= a.Cout) continue;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) out[pixel(i, g, r) * a.Cout + col] = acc[i][g][j][r];
-                }
-        return;
-    }
-    const bool staged = a.y.p && a.Cout % 8 == 0 && a.y.cs % 8 == 0 && a.y.co % 8 == 0;
-    constexpr int BNP = BN + 8;  // padded LDS row of the staged output tile
-    static_assert(TH * TW * BNP * 2 <= NS * SS * 16, "the output tile fits the operand stages");
-    bf16* Cs = reinterpret_cast<bf16*>(lds);
-    if (staged) __syncthreads();  // every wave is done with the operand stages
-#pragma unroll
-    for (int i = 0; i < RW; ++i)
-#pragma unroll
-        for (int g = 0; g < CG; ++g)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int cl = wc * CW + 16 * j + lane % 16, col = n0 + cl;
-                if (col >= a.Cout) continue;
-                const float b = a.bias ? a.bias[col] : 0.f;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = acc[i][g][j][r] + b;
-                    if (a.relu) v = fmaxf(v, 0.f);
-                    if (a.yf) a.yf[pixel(i, g, r) * a.Cout + col] = v;
-                    if (staged)
-                        Cs[((wr * RW + i) * TW + 16 * g + 4 * (lane / 16) + r) * BNP + cl] = bf16(v);
-                    else if (a.y.p)
-                        a.y.p[pixel(i, g, r) * a.y.cs + a.y.co + col] = bf16(v);
-                }
-            }
-    if (!staged) return;
-    __syncthreads();
-    constexpr int G = BN / 8;  // 8-channel chunks per tile pixel
-    for (int c = tid; c < TH * TW * G; c += 256) {
-        const int p = c / G, col = n0 + 8 * (c % G);
-        if (col >= a.Cout) continue;
-        const size_t px = size_t(n * a.H + y0 + p / TW) * a.W + x0 + p % TW;
-        *reinterpret_cast<bf16x8*>(a.y.p + px * a.y.cs + a.y.co + col) =
-            *reinterpret_cast<const bf16x8*>(Cs + p * BNP + 8 * (c % G));
-    }
+    tile_epilogue<TH, TW, BN, WR, NS * SS * 16>(a, acc, lds, n, y0, x0, n0, wr, wc, lane, tid);
 }
 
 __global__ void __launch_bounds__(256) k_split_sum(const ConvArgs a, int splits)
@@ -1007,7 +1068,7 @@ FwdPlan fwd_plan(int N, int H, int W, int Cin, int Cout, int taps)
 {
     FwdPlan f{0, 1, 0};
     const long P = long(N) * H * W;
-    if (taps == 9 && Cin + 32 <= kZeroElems) {
+    if (taps == 9 && Cin + 32 <= kZeroElems && H < (1 << 24) && W < (1 << 24)) {
         auto nb = [&](int th, int tw, int bn) { return long(N) * (H / th) * (W / tw) * ((Cout + bn - 1) / bn); };
         long blocks = 0;
         if (Cout % 64 == 0 && H % 8 == 0 && W % 32 == 0 && nb(8, 32, 64) >= 256) {
