@@ -58,6 +58,7 @@ struct ConvArgs {
     int periodic;       // 1: rows and columns wrap around; 0: zero padding
     float* part;        // split K: fp32 partial sums [splits][pixels][Cout] (null: no split)
     int kper;           // split K: K range of one split (a multiple of TK)
+    Slice pool;         // 2x2 mean of the bf16 output at H/2 x W/2 (p null: none; halo-tile kernel only)
 };
 
 __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, int& x)
@@ -380,6 +381,32 @@ __device__ __forceinline__ void tile_epilogue(const ConvArgs& a, const f4 (&acc)
     for (int k = 0; k < TH * TW / PPI; ++k)
         *reinterpret_cast<bf16x8*>(dst + size_t(k * (PPI / TW)) * W * cs) =
             *reinterpret_cast<const bf16x8*>(src + k * PPI * BNP);
+    if (!a.pool.p) return;
+    // 2x2 mean pooling of the staged tile (the same sums in the same order as k_pool_fwd); item
+    // tid + 256 k is pooled pixel (tid + 256 k) / G, chunk g8 (G divides 256, so the chunk and the
+    // column test above are this thread's for every k)
+    constexpr int TWp = TW / 2, NP = TH * TW / 4;
+    static_assert(TH % 2 == 0 && (NP * G) % 256 == 0, "whole pooled tile per pass count");
+    const size_t Wp = W / 2, ps = size_t(a.pool.cs);
+#pragma unroll
+    for (int k = 0; k < NP * G / 256; ++k) {
+        const int q = (tid + 256 * k) / G, py = q / TWp, px = q % TWp;
+        const bf16* ps0 = Cs + (2 * py * TW + 2 * px) * BNP + 8 * g8;
+        float acc8[8] = {};
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8*>(ps0 + (dy * TW + dx) * BNP);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc8[e] += float(v[e]);
+            }
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = bf16(0.25f * acc8[e]);
+        *reinterpret_cast<bf16x8*>(a.pool.p + ((size_t(n) * (a.H / 2) + y0 / 2 + py) * Wp + x0 / 2 + px) * ps +
+                                   a.pool.co + col) = o;
+    }
 }
 
 // 3x3 convolution on spatial tiles (same result as k_conv_fwd<9, ...>, with a.kper in channels).
@@ -1114,11 +1141,22 @@ void launch_tile(const ConvArgs& a, int nsplit, int chunks_per_block, hipStream_
         hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 1>), grid, dim3(256), 0, st, a);
 }
 
+// pool.p non-null: also the 2x2 mean of the bf16 output y (H and W even) into pool, fused into the
+// halo-tile kernel's output stage where that kernel runs unsplit, else a separate pass.
 hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
-                        int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems)
+                        int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems,
+                        Slice pool = Slice{nullptr, 0, 0})
 {
     if (Cin + 8 > kZeroElems || Cin % 8 || Cout < 1) return hipErrorInvalidValue;
-    ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0};
+    if (pool.p && (!y.p || H % 2 || W % 2 || Cout % 8 || pool.cs % 8 || pool.co % 8)) return hipErrorInvalidValue;
+    ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0, Slice{nullptr, 0, 0}};
+    // pooling as a separate pass after the convolution (where the fused form does not apply)
+    auto pool_pass = [&]() {
+        if (!pool.p) return hipGetLastError();
+        hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(size_t(N) * (H / 2) * (W / 2) * Cout / 8)), dim3(256), 0, st,
+                           CSlice{y.p, y.cs, y.co}, pool, N, H, W, Cout);
+        return hipGetLastError();
+    };
     const long P = long(N) * H * W;
     const FwdPlan f = fwd_plan(N, H, W, Cin, Cout, taps);
     // split K over the workspace when the plan asks for it and the workspace holds the partials
@@ -1130,11 +1168,14 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
     const int nsplit = split ? f.splits : 1;
     if (f.kind) {
         const int chunks = ((split ? f.kper : Cin) + TK - 1) / TK;
+        // fused pooling needs the staged bf16 output stage of an unsplit tile launch
+        const bool fuse = pool.p && !split && y.cs % 8 == 0 && y.co % 8 == 0;
+        if (fuse) a.pool = pool;
         if (f.kind == 1) launch_tile<16, 32, 32, 4>(a, nsplit, chunks, st);
         else if (f.kind == 2) launch_tile<8, 32, 64, 2>(a, nsplit, chunks, st);
         else launch_tile<8, 16, 64, 2>(a, nsplit, chunks, st);
         if (split) hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
-        return hipGetLastError();
+        return fuse ? hipGetLastError() : pool_pass();
     }
     if (split) {
         const dim3 grid(unsigned((P + 63) / 64), unsigned((Cout + 63) / 64), unsigned(nsplit));
@@ -1144,7 +1185,7 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         else
             hipLaunchKernelGGL((k_conv_fwd<1, 64, 64, kConvStages>), grid, dim3(256), lds, st, a);
         hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
-        return hipGetLastError();
+        return pool_pass();
     }
     // the largest tile that still leaves about four blocks per compute unit (256 CUs)
     auto nblocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
@@ -1161,7 +1202,7 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         t9 ? go(k_conv_fwd<9, 128, 32, kConvStages>, 128, 32) : go(k_conv_fwd<1, 128, 32, kConvStages>, 128, 32);
     else
         t9 ? go(k_conv_fwd<9, 64, 32, kConvStages>, 64, 32) : go(k_conv_fwd<1, 64, 32, kConvStages>, 64, 32);
-    return hipGetLastError();
+    return pool_pass();
 }
 
 template <typename T>
@@ -1308,10 +1349,11 @@ bool nn_alloc(lbm_nn* n, T** p, size_t elems)
 CSlice cs(const bf16* p, int c, int off = 0) { return CSlice{p, c, off}; }
 Slice sl(bf16* p, int c, int off = 0) { return Slice{p, c, off}; }
 
-hipError_t fwd(lbm_nn* n, const Conv& c, CSlice x, Slice y, float* yf, int N, int H, int W, bool relu)
+hipError_t fwd(lbm_nn* n, const Conv& c, CSlice x, Slice y, float* yf, int N, int H, int W, bool relu,
+               Slice pool = Slice{nullptr, 0, 0})
 {
     return lbm::nn::conv_forward(x, c.w, n->w + c.b_off, y, yf, N, H, W, c.cin, c.cout, c.taps, relu,
-                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems);
+                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems, pool);
 }
 
 hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, int W)
@@ -1662,14 +1704,11 @@ lbm_status lbm_nn_forward(lbm_nn* n, const void* x, float* y, int32_t batch)
     for (int l = 0; l < L; ++l) {  // encoder
         Level& v = n->lv[l];
         LBM_HIP_TRY(fwd(n, v.c1, cs(v.in, v.cin), sl(v.e1, v.C), nullptr, N, v.H, v.W, true));
+        // the second convolution writes the skip slice of the concatenation and the pooled input of
+        // the level below
         const Slice skip = l < L - 1 ? sl(v.cat, chan(n, l + 1) + v.C, chan(n, l + 1)) : sl(v.e2, v.C);
-        LBM_HIP_TRY(fwd(n, v.c2, cs(v.e1, v.C), skip, nullptr, N, v.H, v.W, true));
-        if (l < L - 1) {
-            Level& nx = n->lv[l + 1];
-            hipLaunchKernelGGL(lbm::nn::k_pool_fwd, dim3(lbm::nn::blocks(size_t(N) * nx.H * nx.W * v.C / 8)), dim3(256), 0,
-                               n->stream, CSlice{skip.p, skip.cs, skip.co}, sl(nx.in, v.C), N, v.H, v.W, v.C);
-            LBM_HIP_TRY(hipGetLastError());
-        }
+        const Slice pooled = l < L - 1 ? sl(n->lv[l + 1].in, v.C) : Slice{nullptr, 0, 0};
+        LBM_HIP_TRY(fwd(n, v.c2, cs(v.e1, v.C), skip, nullptr, N, v.H, v.W, true, pooled));
     }
     for (int l = L - 2; l >= 0; --l) {  // decoder
         Level& v = n->lv[l];
