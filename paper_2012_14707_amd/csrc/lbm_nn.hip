@@ -59,6 +59,12 @@ struct ConvArgs {
     float* part;        // split K: fp32 partial sums [splits][pixels][Cout] (null: no split)
     int kper;           // split K: K range of one split (a multiple of TK)
     Slice pool;         // 2x2 mean of the bf16 output at H/2 x W/2 (p null: none; halo-tile kernel only)
+    // a 1x1 convolution of the bf16 output (all Cout = 32 channels) into y1, fp32 [pixels][c1]
+    // (w1 [c1][32], b1 [c1] or null; w1 null: none; 16 x 32 x 32 halo tiles only)
+    const bf16* w1;
+    const float* b1;
+    float* y1;
+    int c1;
 };
 
 __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, int& x)
@@ -373,6 +379,33 @@ __device__ __forceinline__ void tile_epilogue(const ConvArgs& a, const f4 (&acc)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) cw[(i * TW + 16 * g + r) * BNP + 16 * j] = bf16(act(acc[i][g][j][r] + bias[j]));
     __syncthreads();
+    if constexpr (BN == 32) {
+        if (a.w1) {
+            // the 1x1 convolution: one 16x16x32 MFMA per 16 staged pixels (the products and the
+            // order of the pixel-row kernel with one K step); wave w takes a quarter of the pixels
+            constexpr int PW = TH * TW / 4;
+            const int o = lane % 16;
+            bf16x8 wb;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wb[e] = bf16(0.f);
+            if (o < a.c1) wb = *reinterpret_cast<const bf16x8*>(a.w1 + o * 32 + 8 * (lane / 16));
+            const float b1 = (a.b1 && o < a.c1) ? a.b1[o] : 0.f;
+            const int wave = tid / 64;
+#pragma unroll
+            for (int m = 0; m < PW / 16; ++m) {
+                const int pb = wave * PW + 16 * m;
+                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(Cs + (pb + lane % 16) * BNP + 8 * (lane / 16));
+                const f4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, wb, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                if (o < a.c1) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int pl = pb + 4 * (lane / 16) + r;
+                        a.y1[((size_t(n) * a.H + y0 + pl / TW) * W + x0 + pl % TW) * a.c1 + o] = c[r] + b1;
+                    }
+                }
+            }
+        }
+    }
     const int p0 = tid / G, g8 = tid % G, col = n0 + 8 * g8;
     if (col >= a.Cout) return;
     const bf16* src = Cs + p0 * BNP + 8 * g8;
@@ -1143,19 +1176,45 @@ void launch_tile(const ConvArgs& a, int nsplit, int chunks_per_block, hipStream_
 
 // pool.p non-null: also the 2x2 mean of the bf16 output y (H and W even) into pool, fused into the
 // halo-tile kernel's output stage where that kernel runs unsplit, else a separate pass.
+// A 1x1 convolution that follows a forward convolution (w null: none): w [c][Cout] bf16, b [c] or
+// null, y fp32 [pixels][c].
+struct Out1 {
+    const bf16* w;
+    const float* b;
+    float* y;
+    int c;
+};
+
 hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
                         int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems,
-                        Slice pool = Slice{nullptr, 0, 0})
+                        Slice pool = Slice{nullptr, 0, 0}, Out1 o1 = Out1{nullptr, nullptr, nullptr, 0});
+
+// pool.p non-null: also the 2x2 mean of the bf16 output y (H and W even) into pool, fused into the
+// halo-tile kernel's output stage where that kernel runs unsplit, else a separate pass.  o1.w
+// non-null: also the 1x1 convolution o1 of y (no activation), fused the same way for 32-channel
+// outputs, else a separate convolution.
+hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
+                        int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems,
+                        Slice pool, Out1 o1)
 {
     if (Cin + 8 > kZeroElems || Cin % 8 || Cout < 1) return hipErrorInvalidValue;
     if (pool.p && (!y.p || H % 2 || W % 2 || Cout % 8 || pool.cs % 8 || pool.co % 8)) return hipErrorInvalidValue;
-    ConvArgs a{x, w, bias, y, yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0, Slice{nullptr, 0, 0}};
+    if (o1.w && (!y.p || !o1.y || o1.c < 1)) return hipErrorInvalidValue;
+    ConvArgs a{x,       w,       bias, y,  yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0,
+               Slice{nullptr, 0, 0}, nullptr, nullptr, nullptr, 0};
     // pooling as a separate pass after the convolution (where the fused form does not apply)
     auto pool_pass = [&]() {
         if (!pool.p) return hipGetLastError();
         hipLaunchKernelGGL(k_pool_fwd, dim3(blocks(size_t(N) * (H / 2) * (W / 2) * Cout / 8)), dim3(256), 0, st,
                            CSlice{y.p, y.cs, y.co}, pool, N, H, W, Cout);
         return hipGetLastError();
+    };
+    // the 1x1 convolution as a separate pass
+    auto out1_pass = [&]() {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !o1.w) return e;
+        return conv_forward(CSlice{y.p, y.cs, y.co}, o1.w, o1.b, Slice{nullptr, 0, 0}, o1.y, N, H, W, Cout, o1.c, 1,
+                            false, periodic, st, ws, ws_elems);
     };
     const long P = long(N) * H * W;
     const FwdPlan f = fwd_plan(N, H, W, Cin, Cout, taps);
@@ -1169,13 +1228,25 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
     if (f.kind) {
         const int chunks = ((split ? f.kper : Cin) + TK - 1) / TK;
         // fused pooling needs the staged bf16 output stage of an unsplit tile launch
-        const bool fuse = pool.p && !split && y.cs % 8 == 0 && y.co % 8 == 0;
-        if (fuse) a.pool = pool;
+        const bool staged = !split && y.p && Cout % 8 == 0 && y.cs % 8 == 0 && y.co % 8 == 0;
+        const bool fuse_pool = pool.p && staged;
+        const bool fuse_1x1 = o1.w && staged && f.kind == 1 && Cout == 32 && o1.c <= 16;
+        if (fuse_pool) a.pool = pool;
+        if (fuse_1x1) {
+            a.w1 = o1.w;
+            a.b1 = o1.b;
+            a.y1 = o1.y;
+            a.c1 = o1.c;
+        }
         if (f.kind == 1) launch_tile<16, 32, 32, 4>(a, nsplit, chunks, st);
         else if (f.kind == 2) launch_tile<8, 32, 64, 2>(a, nsplit, chunks, st);
         else launch_tile<8, 16, 64, 2>(a, nsplit, chunks, st);
         if (split) hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
-        return fuse ? hipGetLastError() : pool_pass();
+        if (!fuse_pool) {
+            const hipError_t e = pool_pass();
+            if (e != hipSuccess) return e;
+        }
+        return fuse_1x1 ? hipGetLastError() : out1_pass();
     }
     if (split) {
         const dim3 grid(unsigned((P + 63) / 64), unsigned((Cout + 63) / 64), unsigned(nsplit));
@@ -1185,7 +1256,8 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         else
             hipLaunchKernelGGL((k_conv_fwd<1, 64, 64, kConvStages>), grid, dim3(256), lds, st, a);
         hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
-        return pool_pass();
+        const hipError_t e = pool_pass();
+        return e != hipSuccess ? e : out1_pass();
     }
     // the largest tile that still leaves about four blocks per compute unit (256 CUs)
     auto nblocks = [&](int bm, int bn) { return ((P + bm - 1) / bm) * ((Cout + bn - 1) / bn); };
@@ -1202,7 +1274,8 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         t9 ? go(k_conv_fwd<9, 128, 32, kConvStages>, 128, 32) : go(k_conv_fwd<1, 128, 32, kConvStages>, 128, 32);
     else
         t9 ? go(k_conv_fwd<9, 64, 32, kConvStages>, 64, 32) : go(k_conv_fwd<1, 64, 32, kConvStages>, 64, 32);
-    return pool_pass();
+    const hipError_t e = pool_pass();
+    return e != hipSuccess ? e : out1_pass();
 }
 
 template <typename T>
@@ -1350,10 +1423,10 @@ CSlice cs(const bf16* p, int c, int off = 0) { return CSlice{p, c, off}; }
 Slice sl(bf16* p, int c, int off = 0) { return Slice{p, c, off}; }
 
 hipError_t fwd(lbm_nn* n, const Conv& c, CSlice x, Slice y, float* yf, int N, int H, int W, bool relu,
-               Slice pool = Slice{nullptr, 0, 0})
+               Slice pool = Slice{nullptr, 0, 0}, lbm::nn::Out1 o1 = lbm::nn::Out1{nullptr, nullptr, nullptr, 0})
 {
     return lbm::nn::conv_forward(x, c.w, n->w + c.b_off, y, yf, N, H, W, c.cin, c.cout, c.taps, relu,
-                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems, pool);
+                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems, pool, o1);
 }
 
 hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, int W)
@@ -1719,10 +1792,12 @@ lbm_status lbm_nn_forward(lbm_nn* n, const void* x, float* y, int32_t batch)
                            n->stream, src, sl(v.cat, ccat, 0), N, below.H, below.W, cup);
         LBM_HIP_TRY(hipGetLastError());
         LBM_HIP_TRY(fwd(n, v.d1, cs(v.cat, ccat), sl(v.d1o, v.C), nullptr, N, v.H, v.W, true));
-        LBM_HIP_TRY(fwd(n, v.d2, cs(v.d1o, v.C), sl(v.d2o, v.C), nullptr, N, v.H, v.W, true));
+        // level 0: the output 1x1 convolution follows the last 3x3 one
+        const lbm::nn::Out1 o1 = l == 0 ? lbm::nn::Out1{n->out.w, n->w + n->out.b_off, n->yout, kOutPad}
+                                        : lbm::nn::Out1{nullptr, nullptr, nullptr, 0};
+        LBM_HIP_TRY(fwd(n, v.d2, cs(v.d1o, v.C), sl(v.d2o, v.C), nullptr, N, v.H, v.W, true, Slice{nullptr, 0, 0}, o1));
     }
-    const CSlice top = L == 1 ? cs(v0.e2, v0.C) : cs(v0.d2o, v0.C);
-    LBM_HIP_TRY(fwd(n, n->out, top, Slice{nullptr, 0, 0}, n->yout, N, v0.H, v0.W, false));
+    if (L == 1) LBM_HIP_TRY(fwd(n, n->out, cs(v0.e2, v0.C), Slice{nullptr, 0, 0}, n->yout, N, v0.H, v0.W, false));
     n->last_n = N;
     if (y) {
         const int oc = n->cfg.out_channels;
