@@ -603,7 +603,7 @@ struct WgradArgs {
     CSlice x;        // layer input, Cin channels
     CSlice dz;       // output gradient, Cout channels
     float* partial;  // [nsplit][taps][Cout][Cin]
-    int N, H, W, Cin, Cout, chunk;  // chunk: pixels per split (a multiple of 64)
+    int N, H, W, Cin, Cout, chunk;  // chunk per split: pixels (a multiple of 64), or halo tiles
     int periodic;
 };
 
@@ -734,6 +734,159 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const WgradArgs a)
                 if (row < a.Cout) out[size_t(row) * a.Cin + col] = acc[i][j][r];
             }
         }
+}
+
+// Weight gradient of a 3x3 convolution on spatial tiles: partial[s][tap][co][ci] = sum over the
+// pixels p of the tiles of split s of dz[p][co] x[p + off(tap)][ci].  A block owns 64 output
+// channels (m0) x 64 input channels (n0) and all nine taps, and walks the 128-pixel tiles
+// (128 / TW rows x TW columns) of its split.  Per tile it stages dz (128 pixel rows) and the input
+// halo tile (periodic or zero edges) in LDS in their natural pixel-major layout with 16-byte direct
+// loads, the next two tiles' loads in flight during the current tile's multiplies (three stages,
+// 52 KB each: one block per CU).  The
+// GEMM has M = co, N = ci, K = pixels; its operands need eight consecutive pixels per lane, which
+// the LDS transpose read (ds_read_b64_tr_b16) gives from pixel rows: within 16 lanes, lane i
+// receives element i % 4 of the 8-byte chunks addressed by lanes 4 e + i / 4 (e < 4), so lanes
+// addressing pixel rows P0 + j / 4 at channels c0 + 4 (j % 4) hand lane i channel c0 + i of pixels
+// P0 .. P0 + 3.  K element e of lane group q maps to tile pixel 32 s + 16 (e / 4) + 4 q + e % 4;
+// a tap shifts the input rows read, not their alignment.  Rows are 160 bytes (64 channels, 32
+// bytes of padding): the 8 or 16 consecutive rows of one read then fall in distinct banks at any
+// shift.  Wave w multiplies input-channel group w (16 channels) for every tap and each of the NG
+// output groups (NG = 2 when the layer has at most 32 output channels): nine operand reads of x
+// and NG of dz feed 9 NG MFMAs per 32 pixels.
+constexpr int kWgRow = 10;  // 16-byte slots per LDS row
+
+template <int TW, int NG>
+__global__ void __launch_bounds__(256) k_wgrad_tile(const WgradArgs a)
+{
+    constexpr int TH = 128 / TW, HW = TW + 2, HP = (TH + 2) * HW, PT = TH * TW;
+    constexpr int JD = (kWgRow * PT + 255) / 256, JX = (kWgRow * HP + 255) / 256;
+    constexpr int SD = JD * 256, SS = SD + JX * 256;  // 16-byte slots: dz part, one stage
+    constexpr int NS = 3;
+    static_assert(PT == 128 && TW % 16 == 0, "128-pixel tiles of whole 16-pixel row segments");
+    static_assert(NS * SS * 16 <= 163840, "LDS");
+    __shared__ __align__(16) bf16x8 lds[NS * SS];
+    const int tid = threadIdx.x, lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int tiles_x = a.W / TW, tiles_y = a.H / TH, ntiles = a.N * tiles_y * tiles_x;
+    const int t_begin = blockIdx.z * a.chunk, t_end = min(ntiles, t_begin + a.chunk);
+    const bf16* zero = g_zero;
+    // slot 256 j + t: row (256 j + t) / 10 and 8-channel group (256 j + t) % 10 (8, 9: padding).
+    // The tile-independent part of each slot's source, set once: dz slots keep their element offset
+    // from the tile's first pixel, x slots their halo coordinates (hy << 16 | hx) and channel
+    // offset; -1 marks padding, rows past the tile and channels past the tensor (zeros).
+    int doff[JD], xhw[JX], xoff[JX];
+#pragma unroll
+    for (int j = 0; j < JD; ++j) {
+        const int sl = 256 * j + tid, r = sl / kWgRow, q = sl - r * kWgRow;
+        const bool in = q < 8 && r < PT && m0 + 8 * q < a.Cout;
+        doff[j] = in ? ((r / TW) * a.W + r % TW) * a.dz.cs + a.dz.co + m0 + 8 * q : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < JX; ++j) {
+        const int sl = 256 * j + tid, r = sl / kWgRow, q = sl - r * kWgRow;
+        const bool in = q < 8 && r < HP && n0 + 8 * q < a.Cin;
+        xhw[j] = in ? ((r / HW) << 16) | (r % HW) : -1;
+        xoff[j] = a.x.co + n0 + 8 * q;
+    }
+    auto issue = [&](int tl, int stage) __attribute__((always_inline)) {
+        const int tx = tl % tiles_x, ty = (tl / tiles_x) % tiles_y, n = tl / (tiles_x * tiles_y);
+        const int y0 = ty * TH, x0 = tx * TW;
+        const int img = n * a.H * a.W;
+        const bf16* dzb = a.dz.p + size_t(img + y0 * a.W + x0) * a.dz.cs;  // the tile's first pixel
+        bf16x8* D = lds + stage * SS + 64 * wave;
+#pragma unroll
+        for (int j = 0; j < JD; ++j) {
+            const bf16* src = doff[j] >= 0 ? dzb + doff[j] : zero;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(D + 256 * j), 16, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < JX; ++j) {
+            int yy = y0 - 1 + (xhw[j] >> 16), xx = x0 - 1 + (xhw[j] & 0xffff);
+            if (a.periodic) {
+                yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+            }
+            const bool in = xhw[j] >= 0 && unsigned(yy) < unsigned(a.H) && unsigned(xx) < unsigned(a.W);
+            const unsigned pix = unsigned(img) + __umul24(unsigned(yy), unsigned(a.W)) + unsigned(xx);
+            const bf16* src = in ? a.x.p + size_t(pix) * unsigned(a.x.cs) + xoff[j] : zero;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(D + SD + 256 * j), 16, 0, 0);
+        }
+    };
+
+    typedef __attribute__((address_space(3))) __bf16 lbf16;
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) bf16x4 lbf16x4;
+    auto tr = [&](const lbf16* p) __attribute__((always_inline)) {
+        return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lbf16x4*)p);
+    };
+    // lane (group q, index j): pixel row 4 q + j / 4 of each 16-pixel half step, channels 4 (j % 4)
+    const int q = lane / 16, jr = (lane % 16) / 4, jc = 4 * (lane % 4);
+    // (a wave whose input-channel group lies past the tensor multiplies zeros on its own SIMD and
+    // stores nothing)
+    f4 acc[9][NG];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[t][g] = f4{0.f, 0.f, 0.f, 0.f};
+
+    if (t_begin < t_end) issue(t_begin, 0);
+    if (t_begin + 1 < t_end) issue(t_begin + 1, 1);
+    for (int tl = t_begin, k = 0; tl < t_end; ++tl, ++k) {
+        // this thread's loads of tile k have landed once at most those of tile k + 1 are
+        // outstanding (loads complete in order; no stores in the loop)
+        if (tl + 1 < t_end) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(JD + JX) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // every wave is past tile k - 1: its stage takes tile k + 2
+        if (tl + 2 < t_end) issue(tl + 2, (k + 2) % NS);
+        const lbf16* St = (const lbf16*)(lds + (k % NS) * SS);
+        {
+#pragma unroll
+            for (int s = 0; s < PT / 32; ++s) {
+                // every operand read of the K step first (22 or 26 transpose reads), so that their
+                // latency is paid once rather than before each tap's MFMAs
+                bf16x4 alo[NG], ahi[NG], blo[9], bhi[9];
+                const int p0 = 32 * s + 4 * q + jr, p1 = p0 + 16;  // tile pixels of the two halves
+                const int x0r = (p0 / TW + 1) * HW + p0 % TW + 1, x1r = (p1 / TW + 1) * HW + p1 % TW + 1;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    alo[g] = tr(St + p0 * (8 * kWgRow) + 16 * g + jc);
+                    ahi[g] = tr(St + p1 * (8 * kWgRow) + 16 * g + jc);
+                }
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    const lbf16* X = St + SD * 8 + 16 * wave + jc + ((t / 3 - 1) * HW + (t % 3 - 1)) * (8 * kWgRow);
+                    blo[t] = tr(X + x0r * (8 * kWgRow));
+                    bhi[t] = tr(X + x1r * (8 * kWgRow));
+                }
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    const bf16x8 fb = {blo[t][0], blo[t][1], blo[t][2], blo[t][3], bhi[t][0], bhi[t][1], bhi[t][2], bhi[t][3]};
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        const bf16x8 fa = {alo[g][0], alo[g][1], alo[g][2], alo[g][3], ahi[g][0], ahi[g][1], ahi[g][2], ahi[g][3]};
+                        acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[t][g], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+    // C: lane holds input channel n0 + 16 wave + lane % 16 of output channels m0 + 16 g + 4 q + r
+    const int ci = n0 + 16 * wave + lane % 16;
+    if (ci >= a.Cin) return;
+    float* out = a.partial + size_t(blockIdx.z) * 9 * size_t(a.Cout) * a.Cin + ci;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = m0 + 16 * g + 4 * q + r;
+                if (co < a.Cout) out[(size_t(t) * a.Cout + co) * a.Cin] = acc[t][g][r];
+            }
 }
 
 // grad[e] = sum over k < nsplit of partial[k][e]: 32 elements per block, eight lanes per element
@@ -1296,21 +1449,41 @@ hipError_t conv_dgrad(CSlice dz, const bf16* wt, Slice dx, int N, int H, int W, 
 
 struct WgradPlan {
     int nsplit, chunk, nb, bchunk;
+    int tile_w;  // 32 or 16: the halo-tile kernel with 128-pixel tiles that wide (chunk in tiles); 0:
+                 // the pixel-row kernel (chunk in pixels)
     size_t per, elems;
 };
 
-// Split of the pixel range: enough (tap, tile, split) blocks to fill the chip (about 1024), at
-// least 256 pixels per split.  elems = workspace (split partials + bias partials).
-WgradPlan wgrad_plan(int P, int Cin, int Cout, int taps)
+// 3x3 weight gradients of images that are a whole number of 128-pixel tiles take the halo-tile
+// kernel, split over the tiles for about 256 blocks (one per CU; at most 256 splits, at least two
+// tiles each);
+// the others the pixel-row kernel, split over the pixels for about 1024 (tap, tile, split) blocks,
+// at least 256 pixels per split.  elems = workspace (split partials + bias partials).
+WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int taps)
 {
     WgradPlan w{};
+    const int P = N * H * W;
+    w.nb = std::min(256, (P + 255) / 256);  // bias partials: at most 256 pixel chunks
+    w.bchunk = (P + w.nb - 1) / w.nb;
+    w.per = size_t(taps) * Cout * Cin;
+    if (taps == 9 && H < (1 << 24) && W < (1 << 24)) {
+        if (W % 32 == 0 && H % 4 == 0) w.tile_w = 32;
+        else if (W % 16 == 0 && H % 8 == 0) w.tile_w = 16;
+    }
+    if (w.tile_w) {
+        const int ntiles = N * (H / (128 / w.tile_w)) * (W / w.tile_w);
+        const int blocks = ((Cout + 63) / 64) * ((Cin + 63) / 64);
+        int s = std::min(256, std::max(1, (256 + blocks - 1) / blocks));
+        s = std::min(s, std::max(1, ntiles / 2));
+        w.chunk = (ntiles + s - 1) / s;
+        w.nsplit = (ntiles + w.chunk - 1) / w.chunk;
+        w.elems = size_t(w.nsplit) * w.per + size_t(w.nb) * Cout;
+        return w;
+    }
     const int tiles = taps * ((Cout + TM - 1) / TM) * ((Cin + TN - 1) / TN);
     const int target = std::max(1, std::min(1024 / tiles, P / 256));
     w.chunk = ((P + target - 1) / target + TKW - 1) / TKW * TKW;
     w.nsplit = std::max(1, (P + w.chunk - 1) / w.chunk);
-    w.nb = std::min(256, (P + 255) / 256);  // bias partials: at most 256 pixel chunks
-    w.bchunk = (P + w.nb - 1) / w.nb;
-    w.per = size_t(taps) * Cout * Cin;
     w.elems = size_t(target) * w.per + size_t(w.nb) * Cout;
     return w;
 }
@@ -1319,13 +1492,26 @@ hipError_t conv_wgrad(CSlice x, CSlice dz, float* dw, float* db, float* work, in
                       int taps, bool periodic, hipStream_t st)
 {
     const int P = N * H * W;
-    const WgradPlan pl = wgrad_plan(P, Cin, Cout, taps);
+    const WgradPlan pl = wgrad_plan(N, H, W, Cin, Cout, taps);
     WgradArgs a{x, dz, work, N, H, W, Cin, Cout, pl.chunk, periodic ? 1 : 0};
-    const dim3 grid((Cout + TM - 1) / TM, (Cin + TN - 1) / TN, taps * pl.nsplit);
-    if (taps == 9)
-        hipLaunchKernelGGL(k_conv_wgrad<9>, grid, dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, a);
+    if (pl.tile_w) {
+        const dim3 grid((Cout + 63) / 64, (Cin + 63) / 64, pl.nsplit);
+        const bool two = Cout <= 32;  // two output groups of 16 cover the layer
+        if (pl.tile_w == 32 && two)
+            hipLaunchKernelGGL((k_wgrad_tile<32, 2>), grid, dim3(256), 0, st, a);
+        else if (pl.tile_w == 32)
+            hipLaunchKernelGGL((k_wgrad_tile<32, 4>), grid, dim3(256), 0, st, a);
+        else if (two)
+            hipLaunchKernelGGL((k_wgrad_tile<16, 2>), grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_wgrad_tile<16, 4>), grid, dim3(256), 0, st, a);
+    } else {
+        const dim3 grid((Cout + TM - 1) / TM, (Cin + TN - 1) / TN, taps * pl.nsplit);
+        if (taps == 9)
+            hipLaunchKernelGGL(k_conv_wgrad<9>, grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, a);
+    }
     hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((pl.per + 31) / 32)), dim3(256), 0, st, work, pl.nsplit, pl.per, dw);
     if (db) {
         float* bpart = work + size_t(pl.nsplit) * pl.per;
@@ -1581,7 +1767,7 @@ lbm_status lbm_conv2d_wgrad_workspace(int32_t n, int32_t h, int32_t wd, int32_t 
 {
     if (!elems) return fail(LBM_E_INVAL, "null argument");
     if (!conv_sizes_ok(n, h, wd, cin, cout, ksize)) return fail(LBM_E_INVAL, "convolution sizes out of range");
-    *elems = int64_t(lbm::nn::wgrad_plan(n * h * wd, cin, cout, ksize * ksize).elems);
+    *elems = int64_t(lbm::nn::wgrad_plan(n, h, wd, cin, cout, ksize * ksize).elems);
     return LBM_OK;
 }
 
@@ -1670,12 +1856,11 @@ lbm_status lbm_nn_create(const lbm_nn_config* cfg, uint64_t seed, void* stream, 
         if (ok && l == L - 1) ok = nn_alloc(n, &v.e2, px * v.C) && nn_alloc(n, &v.g_e2, px * v.C);
     }
     for (const Conv* cv : n->convs) {
-        const int P = int(B) * n->lv[cv->level].H * n->lv[cv->level].W;
-        work = std::max(work, lbm::nn::wgrad_plan(P, cv->cin, cv->cout, cv->taps).elems);
-        // split-K partial sums of the forward and of the input gradient (channel roles exchanged)
-        // (for every batch size up to the maximum: smaller batches split more ways)
+        // weight-gradient split partials, split-K partial sums of the forward and of the input
+        // gradient (channel roles exchanged), for every batch size up to the maximum
         const int lh = n->lv[cv->level].H, lw = n->lv[cv->level].W;
         for (int nb = 1; nb <= int(B); ++nb) {
+            work = std::max(work, lbm::nn::wgrad_plan(nb, lh, lw, cv->cin, cv->cout, cv->taps).elems);
             work = std::max(work, lbm::nn::fwd_split_elems(nb, lh, lw, cv->cin, cv->cout, cv->taps));
             work = std::max(work, lbm::nn::fwd_split_elems(nb, lh, lw, cv->cout, cv->cin, cv->taps));
         }
