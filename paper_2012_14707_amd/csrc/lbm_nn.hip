@@ -889,21 +889,40 @@ __global__ void __launch_bounds__(256) k_wgrad_tile(const WgradArgs a)
             }
 }
 
-// grad[e] = sum over k < nsplit of partial[k][e]: 32 elements per block, eight lanes per element
-// summing interleaved k, then a butterfly over the eight lanes (every lane forms the same sums in
-// the same order, so the result does not depend on scheduling).  One thread per element walking
-// all k was bound by the latency of its dependent loads.
+// grad[e] = sum over k < nsplit of partial[k][e]: L lanes per element (256 / L elements per block)
+// summing interleaved k, then a butterfly over the L lanes (every lane forms the same sums in the
+// same order, so the result does not depend on scheduling).  L = 8 keeps each load coalesced over
+// eight consecutive elements; L = 64 (a wave per element) serves short outputs summed over many
+// partials.  One thread per element walking all k was bound by the latency of its dependent loads.
+template <int L>
 __global__ void __launch_bounds__(256) k_sum_splits(const float* partial, int nsplit, size_t n, float* grad)
 {
-    const int l = threadIdx.x & 7;
-    const size_t e = size_t(blockIdx.x) * 32 + (threadIdx.x >> 3);
+    const int l = threadIdx.x % L;
+    const size_t e = size_t(blockIdx.x) * (256 / L) + threadIdx.x / L;
     float s = 0.f;
-    if (e < n)
-        for (int k = l; k < nsplit; k += 8) s += partial[size_t(k) * n + e];
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
+    if (e < n) {
+        // four partial sums (k = l + L (4 i + u)) keep four loads in flight, then combined in order
+        float u4[4] = {0.f, 0.f, 0.f, 0.f};
+        int k = l;
+        for (; k + 3 * L < nsplit; k += 4 * L)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) u4[u] += partial[size_t(k + L * u) * n + e];
+        if (k < nsplit) u4[0] += partial[size_t(k) * n + e];
+        if (k + L < nsplit) u4[1] += partial[size_t(k + L) * n + e];
+        if (k + 2 * L < nsplit) u4[2] += partial[size_t(k + 2 * L) * n + e];
+        s = (u4[0] + u4[1]) + (u4[2] + u4[3]);
+    }
+#pragma unroll
+    for (int m = 1; m < L; m *= 2) s += __shfl_xor(s, m);
     if (e < n && l == 0) grad[e] = s;
+}
+
+void sum_splits(const float* partial, int nsplit, size_t n, float* grad, hipStream_t st)
+{
+    if (n <= 4096 && nsplit >= 256)
+        hipLaunchKernelGGL(k_sum_splits<64>, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, partial, nsplit, n, grad);
+    else
+        hipLaunchKernelGGL(k_sum_splits<8>, dim3(unsigned((n + 31) / 32)), dim3(256), 0, st, partial, nsplit, n, grad);
 }
 
 // Bias gradient partials: part[b][co] = sum of dz[p][co] over the pixels p of chunk b (chunk pixels
@@ -959,6 +978,40 @@ __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<
 __device__ __forceinline__ void st8(bf16* p, bf16x8 v) { *reinterpret_cast<bf16x8*>(p) = v; }
 
 // dz[p][c] = g[p][c] if y[p][c] > 0 else 0 (ReLU backward; dz contiguous with C channels)
+// ReLU backward (as k_relu_bwd) with the bias gradient's partial sums: part[b][c] = sum of dz[p][c]
+// over the pixels p of chunk b.  A block owns one chunk; thread t takes the 8-channel group
+// t % G of the pixels t / G, t / G + L, ... (L = 256 / G pixel lanes, G = C / 8 <= 256), then the
+// L lanes of each group are summed in lane order through LDS (the same sums on every run).
+__global__ void __launch_bounds__(256) k_relu_bwd_bias(CSlice g, CSlice y, bf16* dz, int P, int C, int chunk,
+                                                      float* part)
+{
+    __shared__ float red[256][9];
+    const int G = C / 8, L = 256 / G;
+    const int cg = threadIdx.x % G, lane = threadIdx.x / G, c = 8 * cg;
+    float s[8] = {};
+    const int p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+    if (lane < L)
+        for (int p = p0 + lane; p < p1; p += L) {
+            const bf16x8 yv = ld8(y.p + size_t(p) * y.cs + y.co + c), gv = ld8(g.p + size_t(p) * g.cs + g.co + c);
+            bf16x8 o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                o[k] = float(yv[k]) > 0.f ? gv[k] : bf16(0.f);
+                s[k] += float(o[k]);
+            }
+            st8(dz + size_t(p) * C + c, o);
+        }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = s[k];
+    __syncthreads();
+    for (int o = threadIdx.x; o < C; o += 256) {
+        const int og = o / 8, ok = o % 8;
+        float t = 0.f;
+        for (int l = 0; l < L; ++l) t += red[l * G + og][ok];
+        part[size_t(blockIdx.x) * C + o] = t;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_relu_bwd(CSlice g, CSlice y, bf16* dz, int P, int C)
 {
     const int G = C / 8;
@@ -1512,12 +1565,11 @@ hipError_t conv_wgrad(CSlice x, CSlice dz, float* dw, float* db, float* work, in
         else
             hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, a);
     }
-    hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((pl.per + 31) / 32)), dim3(256), 0, st, work, pl.nsplit, pl.per, dw);
+    sum_splits(work, pl.nsplit, pl.per, dw, st);
     if (db) {
         float* bpart = work + size_t(pl.nsplit) * pl.per;
         hipLaunchKernelGGL(k_bias_partial, dim3(pl.nb), dim3(256), 0, st, dz, P, Cout, pl.bchunk, bpart);
-        hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((Cout + 31) / 32)), dim3(256), 0, st, bpart, pl.nb,
-                           size_t(Cout), db);
+        sum_splits(bpart, pl.nb, size_t(Cout), db, st);
     }
     return hipGetLastError();
 }
@@ -1623,15 +1675,32 @@ hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, in
 
 // Backward of one convolution + ReLU.  g: gradient w.r.t. its output y (after ReLU), x: its
 // input.  Writes its weight and bias gradients and, if gx.p, the gradient w.r.t. x.
+// pixel chunks of the fused ReLU / bias-gradient pass: up to 1024 blocks, at least 128 pixels each
+int relu_bias_chunks(int P) { return std::max(1, std::min(1024, (P + 127) / 128)); }
+
 hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g, Slice gx, int N, int H, int W)
 {
     const int P = N * H * W;
-    hipLaunchKernelGGL(lbm::nn::k_relu_bwd, dim3(lbm::nn::blocks(size_t(P) * c.cout / 8)), dim3(256), 0, n->stream, g, y,
-                       n->dz, P, c.cout);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const CSlice dz = cs(n->dz, c.cout);
-    e = wgrad(n, c, x, dz, N, H, W);
+    hipError_t e;
+    if (c.cout <= 2048) {
+        // ReLU backward with the bias gradient's chunk partials (in the workspace, summed before
+        // the weight gradient reuses it), then the weight gradient alone
+        const int nb = relu_bias_chunks(P), chunk = (P + nb - 1) / nb;
+        hipLaunchKernelGGL(lbm::nn::k_relu_bwd_bias, dim3(nb), dim3(256), 0, n->stream, g, y, n->dz, P, c.cout, chunk,
+                           n->work);
+        lbm::nn::sum_splits(n->work, nb, size_t(c.cout), n->g + c.b_off, n->stream);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = lbm::nn::conv_wgrad(x, dz, n->g + c.w_off, nullptr, n->work, N, H, W, c.cin, c.cout, c.taps,
+                                n->cfg.periodic != 0, n->stream);
+    } else {
+        hipLaunchKernelGGL(lbm::nn::k_relu_bwd, dim3(lbm::nn::blocks(size_t(P) * c.cout / 8)), dim3(256), 0, n->stream,
+                           g, y, n->dz, P, c.cout);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = wgrad(n, c, x, dz, N, H, W);
+    }
     if (e != hipSuccess || !gx.p) return e;
     return lbm::nn::conv_dgrad(dz, c.wt, gx, N, H, W, c.cin, c.cout, c.taps, n->cfg.periodic != 0, n->stream,
                                n->work, n->work_elems);
@@ -1861,6 +1930,7 @@ lbm_status lbm_nn_create(const lbm_nn_config* cfg, uint64_t seed, void* stream, 
         const int lh = n->lv[cv->level].H, lw = n->lv[cv->level].W;
         for (int nb = 1; nb <= int(B); ++nb) {
             work = std::max(work, lbm::nn::wgrad_plan(nb, lh, lw, cv->cin, cv->cout, cv->taps).elems);
+            work = std::max(work, size_t(relu_bias_chunks(nb * lh * lw)) * size_t(cv->cout));
             work = std::max(work, lbm::nn::fwd_split_elems(nb, lh, lw, cv->cin, cv->cout, cv->taps));
             work = std::max(work, lbm::nn::fwd_split_elems(nb, lh, lw, cv->cout, cv->cin, cv->taps));
         }
