@@ -65,6 +65,10 @@ struct ConvArgs {
     const float* b1;
     float* y1;
     int c1;
+    // input channels [0, cup) are the nearest 2x upsampling of up (an H/2 x W/2 image; p null:
+    // none; halo-tile kernel only); channels >= cup are read from x
+    CSlice up;
+    int cup;
 };
 
 __device__ __forceinline__ void decompose(int p, int H, int W, int& n, int& y, int& x)
@@ -479,21 +483,34 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
     const bf16* asrc[JA];
     const bf16* bsrc[JB];
     int aq8[JA], bq8[JB];
-    const unsigned img = unsigned(n) * unsigned(a.H) * unsigned(a.W);  // first pixel of image n
+    // input sources of the halo slots: x, or (chunks below a.cup) the upsampled low-resolution
+    // image, whose pixel (yy / 2, xx / 2) a full-resolution pixel repeats
+    auto set_a = [&](bool from_up) __attribute__((always_inline)) {
+        const unsigned img = unsigned(n) * unsigned(a.H) * unsigned(a.W);  // first pixel of image n
+        const unsigned Wl = unsigned(a.W / 2), imgl = unsigned(n) * unsigned(a.H / 2) * Wl;
 #pragma unroll
-    for (int j = 0; j < JA; ++j) {
-        const int sl = 256 * j + tid, r = sl / kTileRow, q = sl - r * kTileRow;
-        const int hy = r / HW, hx = r - hy * HW;
-        int yy = y0 - 1 + hy, xx = x0 - 1 + hx;
-        if (a.periodic) {
-            yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
-            xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+        for (int j = 0; j < JA; ++j) {
+            const int sl = 256 * j + tid, r = sl / kTileRow, q = sl - r * kTileRow;
+            const int hy = r / HW, hx = r - hy * HW;
+            int yy = y0 - 1 + hy, xx = x0 - 1 + hx;
+            if (a.periodic) {
+                yy = yy < 0 ? yy + a.H : (yy >= a.H ? yy - a.H : yy);
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+            }
+            const bool in = q < 4 && r < HP && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            aq8[j] = q < 4 ? 8 * q : 0;
+            const bf16* src;
+            if (from_up) {
+                const unsigned pl = imgl + __umul24(unsigned(yy >> 1), Wl) + unsigned(xx >> 1);
+                src = in ? a.up.p + size_t(pl) * unsigned(a.up.cs) + a.up.co : zero;
+            } else {
+                const unsigned pix = img + __umul24(unsigned(yy), unsigned(a.W)) + unsigned(xx);
+                src = in ? a.x.p + size_t(pix) * unsigned(a.x.cs) + a.x.co : zero;
+            }
+            asrc[j] = src + aq8[j];
         }
-        const bool in = q < 4 && r < HP && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-        const unsigned pix = img + __umul24(unsigned(yy), unsigned(a.W)) + unsigned(xx);
-        aq8[j] = q < 4 ? 8 * q : 0;
-        asrc[j] = (in ? a.x.p + size_t(pix) * unsigned(a.x.cs) + a.x.co : zero) + aq8[j];
-    }
+    };
+    set_a(a.up.p && c_begin < a.cup);
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
         const int sl = 256 * j + tid, r = sl / kTileRow, q = sl - r * kTileRow;
@@ -506,6 +523,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
     auto issue = [&](int step) __attribute__((always_inline)) {
         bf16x8* A = lds + (step % NS) * SS + 64 * wave;
         const int c = c_begin + step * TK;
+        if (a.up.p && step > 0 && c == a.cup) set_a(false);  // the skip channels start here
         if (c + TK <= c_end) {
 #pragma unroll
             for (int j = 0; j < JA; ++j) {
@@ -605,6 +623,10 @@ struct WgradArgs {
     float* partial;  // [nsplit][taps][Cout][Cin]
     int N, H, W, Cin, Cout, chunk;  // chunk per split: pixels (a multiple of 64), or halo tiles
     int periodic;
+    // input channels [0, cup) are the nearest 2x upsampling of up (H/2 x W/2; p null: none;
+    // halo-tile kernel only, cup a multiple of 64)
+    CSlice up;
+    int cup;
 };
 
 // partial[s][tap][co][ci] = sum over the pixels p of split s of dz[p][co] x[p + off(tap)][ci].
@@ -776,6 +798,11 @@ __global__ void __launch_bounds__(256) k_wgrad_tile(const WgradArgs a)
     // from the tile's first pixel, x slots their halo coordinates (hy << 16 | hx) and channel
     // offset; -1 marks padding, rows past the tile and channels past the tensor (zeros).
     int doff[JD], xhw[JX], xoff[JX];
+    // this block's input channels come from x or, below a.cup, from the upsampled low-resolution
+    // image (pixel (yy / 2, xx / 2))
+    const bool from_up = a.up.p && n0 < a.cup;
+    const bf16* xsrc = from_up ? a.up.p : a.x.p;
+    const unsigned xcs = unsigned(from_up ? a.up.cs : a.x.cs);
 #pragma unroll
     for (int j = 0; j < JD; ++j) {
         const int sl = 256 * j + tid, r = sl / kWgRow, q = sl - r * kWgRow;
@@ -787,7 +814,7 @@ __global__ void __launch_bounds__(256) k_wgrad_tile(const WgradArgs a)
         const int sl = 256 * j + tid, r = sl / kWgRow, q = sl - r * kWgRow;
         const bool in = q < 8 && r < HP && n0 + 8 * q < a.Cin;
         xhw[j] = in ? ((r / HW) << 16) | (r % HW) : -1;
-        xoff[j] = a.x.co + n0 + 8 * q;
+        xoff[j] = (from_up ? a.up.co : a.x.co) + n0 + 8 * q;
     }
     auto issue = [&](int tl, int stage) __attribute__((always_inline)) {
         const int tx = tl % tiles_x, ty = (tl / tiles_x) % tiles_y, n = tl / (tiles_x * tiles_y);
@@ -808,8 +835,9 @@ __global__ void __launch_bounds__(256) k_wgrad_tile(const WgradArgs a)
                 xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
             }
             const bool in = xhw[j] >= 0 && unsigned(yy) < unsigned(a.H) && unsigned(xx) < unsigned(a.W);
-            const unsigned pix = unsigned(img) + __umul24(unsigned(yy), unsigned(a.W)) + unsigned(xx);
-            const bf16* src = in ? a.x.p + size_t(pix) * unsigned(a.x.cs) + xoff[j] : zero;
+            const unsigned pix = from_up ? unsigned(img / 4) + __umul24(unsigned(yy >> 1), unsigned(a.W / 2)) + unsigned(xx >> 1)
+                                         : unsigned(img) + __umul24(unsigned(yy), unsigned(a.W)) + unsigned(xx);
+            const bf16* src = in ? xsrc + size_t(pix) * xcs + xoff[j] : zero;
             __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(D + SD + 256 * j), 16, 0, 0);
         }
     };
@@ -1382,6 +1410,23 @@ void launch_tile(const ConvArgs& a, int nsplit, int chunks_per_block, hipStream_
 
 // pool.p non-null: also the 2x2 mean of the bf16 output y (H and W even) into pool, fused into the
 // halo-tile kernel's output stage where that kernel runs unsplit, else a separate pass.
+// Input channels [0, cup) given as the nearest 2x upsampling of src (an H/2 x W/2 image; p null:
+// none).  cat is where the input tensor keeps those channels: the convolutions read them from src
+// where their halo-tile kernels run, and the upsampled values are written to cat first otherwise.
+struct UpSrc {
+    CSlice src;
+    int cup;
+    Slice cat;
+};
+
+// writes the upsampled channels into cat when a kernel needs them there
+hipError_t materialize(const UpSrc& u, int N, int H, int W, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_up_fwd, dim3(blocks(size_t(N) * H * W * u.cup / 8)), dim3(256), 0, st, u.src, u.cat, N, H / 2,
+                       W / 2, u.cup);
+    return hipGetLastError();
+}
+
 // A 1x1 convolution that follows a forward convolution (w null: none): w [c][Cout] bf16, b [c] or
 // null, y fp32 [pixels][c].
 struct Out1 {
@@ -1393,7 +1438,8 @@ struct Out1 {
 
 hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
                         int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems,
-                        Slice pool = Slice{nullptr, 0, 0}, Out1 o1 = Out1{nullptr, nullptr, nullptr, 0});
+                        Slice pool = Slice{nullptr, 0, 0}, Out1 o1 = Out1{nullptr, nullptr, nullptr, 0},
+                        UpSrc up = UpSrc{CSlice{nullptr, 0, 0}, 0, Slice{nullptr, 0, 0}});
 
 // pool.p non-null: also the 2x2 mean of the bf16 output y (H and W even) into pool, fused into the
 // halo-tile kernel's output stage where that kernel runs unsplit, else a separate pass.  o1.w
@@ -1401,13 +1447,14 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
 // outputs, else a separate convolution.
 hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, float* yf, int N, int H, int W, int Cin,
                         int Cout, int taps, bool relu, bool periodic, hipStream_t st, float* ws, size_t ws_elems,
-                        Slice pool, Out1 o1)
+                        Slice pool, Out1 o1, UpSrc up)
 {
     if (Cin + 8 > kZeroElems || Cin % 8 || Cout < 1) return hipErrorInvalidValue;
     if (pool.p && (!y.p || H % 2 || W % 2 || Cout % 8 || pool.cs % 8 || pool.co % 8)) return hipErrorInvalidValue;
     if (o1.w && (!y.p || !o1.y || o1.c < 1)) return hipErrorInvalidValue;
     ConvArgs a{x,       w,       bias, y,  yf, N, H, W, Cin, Cout, relu ? 1 : 0, periodic ? 1 : 0, nullptr, 0,
-               Slice{nullptr, 0, 0}, nullptr, nullptr, nullptr, 0};
+               Slice{nullptr, 0, 0}, nullptr, nullptr, nullptr, 0, CSlice{nullptr, 0, 0}, 0};
+    if (up.src.p && (H % 2 || W % 2 || up.cup % 8 || up.cup > Cin || !up.cat.p)) return hipErrorInvalidValue;
     // pooling as a separate pass after the convolution (where the fused form does not apply)
     auto pool_pass = [&]() {
         if (!pool.p) return hipGetLastError();
@@ -1424,6 +1471,15 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
     };
     const long P = long(N) * H * W;
     const FwdPlan f = fwd_plan(N, H, W, Cin, Cout, taps);
+    if (up.src.p) {
+        if (f.kind && up.cup % TK == 0) {  // whole chunks from one source
+            a.up = up.src;
+            a.cup = up.cup;
+        } else {
+            const hipError_t e = materialize(up, N, H, W, st);
+            if (e != hipSuccess) return e;
+        }
+    }
     // split K over the workspace when the plan asks for it and the workspace holds the partials
     const bool split = f.splits > 1 && ws && ws_elems >= fwd_split_elems(N, H, W, Cin, Cout, taps);
     if (split) {
@@ -1542,11 +1598,20 @@ WgradPlan wgrad_plan(int N, int H, int W, int Cin, int Cout, int taps)
 }
 
 hipError_t conv_wgrad(CSlice x, CSlice dz, float* dw, float* db, float* work, int N, int H, int W, int Cin, int Cout,
-                      int taps, bool periodic, hipStream_t st)
+                      int taps, bool periodic, hipStream_t st, UpSrc up = UpSrc{CSlice{nullptr, 0, 0}, 0, Slice{nullptr, 0, 0}})
 {
     const int P = N * H * W;
     const WgradPlan pl = wgrad_plan(N, H, W, Cin, Cout, taps);
-    WgradArgs a{x, dz, work, N, H, W, Cin, Cout, pl.chunk, periodic ? 1 : 0};
+    WgradArgs a{x, dz, work, N, H, W, Cin, Cout, pl.chunk, periodic ? 1 : 0, CSlice{nullptr, 0, 0}, 0};
+    if (up.src.p) {
+        if (pl.tile_w && up.cup % 64 == 0 && H % 2 == 0 && W % 2 == 0) {  // whole 64-channel blocks from one source
+            a.up = up.src;
+            a.cup = up.cup;
+        } else {
+            const hipError_t e = materialize(up, N, H, W, st);
+            if (e != hipSuccess) return e;
+        }
+    }
     if (pl.tile_w) {
         const dim3 grid((Cout + 63) / 64, (Cin + 63) / 64, pl.nsplit);
         const bool two = Cout <= 32;  // two output groups of 16 cover the layer
@@ -1660,11 +1725,14 @@ bool nn_alloc(lbm_nn* n, T** p, size_t elems)
 CSlice cs(const bf16* p, int c, int off = 0) { return CSlice{p, c, off}; }
 Slice sl(bf16* p, int c, int off = 0) { return Slice{p, c, off}; }
 
+const lbm::nn::UpSrc kNoUp{CSlice{nullptr, 0, 0}, 0, Slice{nullptr, 0, 0}};
+
 hipError_t fwd(lbm_nn* n, const Conv& c, CSlice x, Slice y, float* yf, int N, int H, int W, bool relu,
-               Slice pool = Slice{nullptr, 0, 0}, lbm::nn::Out1 o1 = lbm::nn::Out1{nullptr, nullptr, nullptr, 0})
+               Slice pool = Slice{nullptr, 0, 0}, lbm::nn::Out1 o1 = lbm::nn::Out1{nullptr, nullptr, nullptr, 0},
+               lbm::nn::UpSrc up = kNoUp)
 {
     return lbm::nn::conv_forward(x, c.w, n->w + c.b_off, y, yf, N, H, W, c.cin, c.cout, c.taps, relu,
-                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems, pool, o1);
+                                 n->cfg.periodic != 0, n->stream, n->work, n->work_elems, pool, o1, up);
 }
 
 hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, int W)
@@ -1678,7 +1746,8 @@ hipError_t wgrad(lbm_nn* n, const Conv& c, CSlice x, CSlice dz, int N, int H, in
 // pixel chunks of the fused ReLU / bias-gradient pass: up to 1024 blocks, at least 128 pixels each
 int relu_bias_chunks(int P) { return std::max(1, std::min(1024, (P + 127) / 128)); }
 
-hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g, Slice gx, int N, int H, int W)
+hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g, Slice gx, int N, int H, int W,
+                         lbm::nn::UpSrc up = kNoUp)
 {
     const int P = N * H * W;
     const CSlice dz = cs(n->dz, c.cout);
@@ -1693,11 +1762,12 @@ hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g,
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = lbm::nn::conv_wgrad(x, dz, n->g + c.w_off, nullptr, n->work, N, H, W, c.cin, c.cout, c.taps,
-                                n->cfg.periodic != 0, n->stream);
+                                n->cfg.periodic != 0, n->stream, up);
     } else {
         hipLaunchKernelGGL(lbm::nn::k_relu_bwd, dim3(lbm::nn::blocks(size_t(P) * c.cout / 8)), dim3(256), 0, n->stream,
                            g, y, n->dz, P, c.cout);
         e = hipGetLastError();
+        if (e == hipSuccess && up.src.p) e = lbm::nn::materialize(up, N, H, W, n->stream);
         if (e != hipSuccess) return e;
         e = wgrad(n, c, x, dz, N, H, W);
     }
@@ -2042,11 +2112,11 @@ lbm_status lbm_nn_forward(lbm_nn* n, const void* x, float* y, int32_t batch)
         Level& v = n->lv[l];
         const Level& below = n->lv[l + 1];
         const int cup = chan(n, l + 1), ccat = cup + v.C;
-        const CSlice src = l == L - 2 ? cs(below.e2, below.C) : cs(below.d2o, below.C);
-        hipLaunchKernelGGL(lbm::nn::k_up_fwd, dim3(lbm::nn::blocks(size_t(N) * v.H * v.W * cup / 8)), dim3(256), 0,
-                           n->stream, src, sl(v.cat, ccat, 0), N, below.H, below.W, cup);
-        LBM_HIP_TRY(hipGetLastError());
-        LBM_HIP_TRY(fwd(n, v.d1, cs(v.cat, ccat), sl(v.d1o, v.C), nullptr, N, v.H, v.W, true));
+        // the first convolution reads the upsampled part of its input straight from the level below
+        // (written into the concatenation only where a kernel needs it there)
+        const lbm::nn::UpSrc up{l == L - 2 ? cs(below.e2, below.C) : cs(below.d2o, below.C), cup, sl(v.cat, ccat, 0)};
+        LBM_HIP_TRY(fwd(n, v.d1, cs(v.cat, ccat), sl(v.d1o, v.C), nullptr, N, v.H, v.W, true, Slice{nullptr, 0, 0},
+                        lbm::nn::Out1{nullptr, nullptr, nullptr, 0}, up));
         // level 0: the output 1x1 convolution follows the last 3x3 one
         const lbm::nn::Out1 o1 = l == 0 ? lbm::nn::Out1{n->out.w, n->w + n->out.b_off, n->yout, kOutPad}
                                         : lbm::nn::Out1{nullptr, nullptr, nullptr, 0};
@@ -2091,8 +2161,9 @@ lbm_status lbm_nn_backward(lbm_nn* n, const float* target, const uint8_t* mask, 
         const int cup = chan(n, l + 1), ccat = cup + v.C;
         LBM_HIP_TRY(conv_relu_bwd(n, v.d2, cs(v.d1o, v.C), cs(v.d2o, v.C), cs(v.g_d2o, v.C), sl(v.g_d1o, v.C), N, v.H,
                                   v.W));
+        const lbm::nn::UpSrc up{l == L - 2 ? cs(below.e2, below.C) : cs(below.d2o, below.C), cup, sl(v.cat, ccat, 0)};
         LBM_HIP_TRY(conv_relu_bwd(n, v.d1, cs(v.cat, ccat), cs(v.d1o, v.C), cs(v.g_d1o, v.C), sl(v.g_cat, ccat), N,
-                                  v.H, v.W));
+                                  v.H, v.W, up));
         // upsampled part of the concatenation -> gradient of the level below's output
         const Slice gsrc = l == L - 2 ? sl(below.g_e2, below.C) : sl(below.g_d2o, below.C);
         hipLaunchKernelGGL(lbm::nn::k_up_bwd, dim3(lbm::nn::blocks(size_t(N) * below.H * below.W * cup / 8)), dim3(256),
