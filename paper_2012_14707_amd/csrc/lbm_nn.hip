@@ -998,6 +998,31 @@ __global__ void __launch_bounds__(256) k_flip(const T* w, bf16* wt, int taps, in
     wt[e] = bf16(float(w[(size_t(taps - 1 - tap) * Cout + co) * Cin + ci]));
 }
 
+// The flips of every convolution of a network in one launch: element e of the concatenation of
+// their wt arrays (convolution k owns [start[k], start[k + 1])), each as k_flip.
+constexpr int kMaxFlip = 32;
+struct FlipTable {
+    int n;
+    size_t start[kMaxFlip + 1];
+    const float* w[kMaxFlip];
+    bf16* wt[kMaxFlip];
+    int taps[kMaxFlip], cout[kMaxFlip], cin[kMaxFlip];
+};
+
+__global__ void __launch_bounds__(256) k_flip_all(const FlipTable t)
+{
+    const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= t.start[t.n]) return;
+    int k = 0;
+    while (e >= t.start[k + 1]) ++k;
+    const size_t l = e - t.start[k];
+    const int Cout = t.cout[k], Cin = t.cin[k], taps = t.taps[k];
+    const int co = int(l % Cout);
+    const size_t q = l / Cout;
+    const int ci = int(q % Cin), tap = int(q / Cin);
+    t.wt[k][l] = bf16(t.w[k][(size_t(taps - 1 - tap) * Cout + co) * Cin + ci]);
+}
+
 // ------------------------------------------------------------------------ elementwise kernels
 
 // The elementwise kernels below move eight channels (one 16-byte bf16x8) per thread: channel counts,
@@ -1778,11 +1803,26 @@ hipError_t conv_relu_bwd(lbm_nn* n, const Conv& c, CSlice x, CSlice y, CSlice g,
 
 hipError_t refresh_flipped(lbm_nn* n)
 {
-    for (Conv* cv : n->convs) {
-        hipError_t e = lbm::nn::flip(n->w + cv->w_off, cv->wt, cv->taps, cv->cout, cv->cin, n->stream);
-        if (e != hipSuccess) return e;
+    if (n->convs.size() > size_t(lbm::nn::kMaxFlip)) {
+        for (Conv* cv : n->convs) {
+            hipError_t e = lbm::nn::flip(n->w + cv->w_off, cv->wt, cv->taps, cv->cout, cv->cin, n->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
-    return hipSuccess;
+    lbm::nn::FlipTable t{};
+    t.n = int(n->convs.size());
+    for (int k = 0; k < t.n; ++k) {
+        const Conv* cv = n->convs[k];
+        t.w[k] = n->w + cv->w_off;
+        t.wt[k] = cv->wt;
+        t.taps[k] = cv->taps;
+        t.cout[k] = cv->cout;
+        t.cin[k] = cv->cin;
+        t.start[k + 1] = t.start[k] + size_t(cv->taps) * cv->cout * cv->cin;
+    }
+    hipLaunchKernelGGL(lbm::nn::k_flip_all, dim3(lbm::nn::blocks(t.start[t.n])), dim3(256), 0, n->stream, t);
+    return hipGetLastError();
 }
 
 bool conv_sizes_ok(int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout, int32_t ksize)
