@@ -149,8 +149,12 @@ def _net_inputs(rng, n, h, w, cin, cout):
     return x, target, mask
 
 
+# (levels, base channels, in, out, batch, height, width, periodic).  The 256^2 network at batch 1
+# splits K in most deep layers (pooling and upsampling then take their separate passes below level
+# 0); at batch 4 levels 1 and 2 run unsplit with the pooling fused into the convolutions, here with
+# zero padding.
 @pytest.mark.parametrize("shape", [(3, 16, 12, 3, 2, 32, 48, False), (3, 16, 12, 3, 2, 32, 48, True),
-                                   (5, 32, 12, 3, 1, 256, 256, True)])
+                                   (5, 32, 12, 3, 1, 256, 256, True), (5, 32, 12, 3, 4, 256, 256, False)])
 def test_network_forward_and_gradients(shape):
     import torch
     from paper_2012_14707_amd import lbm
