@@ -231,6 +231,14 @@ lbm_status lbm_set_launch(lbm_ctx *ctx, int32_t block);
  * LDS staging area. */
 lbm_status lbm_set_fusion(lbm_ctx *ctx, int32_t steps_per_launch, int32_t rows);
 
+/* Step launches by graph replay (on = 1, the default) or one by one (0).  With graphs, lbm_step
+ * captures its launch sequence (at most 256 steps per graph, the last one recording u) once per
+ * (step count, time-level parity) on a private stream of the context and replays it on the
+ * context's stream, which removes the per-launch host cost that dominates small lattices.  Results
+ * are bit-identical either way.  If capture is not possible the context falls back to launches
+ * for good.  Changing the launch configuration or the fusion drops the captured graphs. */
+lbm_status lbm_set_graphs(lbm_ctx *ctx, int32_t on);
+
 /* Device-to-device streaming copy of `bytes` bytes (dst, src: device memory, 16-byte aligned, bytes
  * a multiple of 16, else LBM_E_INVAL), asynchronous on `stream` (hipStream_t, NULL = null stream).
  * A measurement aid, not a step of the method: its bandwidth is the practical streaming ceiling

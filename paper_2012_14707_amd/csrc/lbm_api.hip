@@ -57,6 +57,22 @@ struct lbm_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_timing = false;
     int64_t timed_steps = 0;
+    // lbm_step by graph replay: captured launch sequences, keyed by (steps, parity at the start,
+    // whether the last launch records u), on a private capture stream; replayed on `stream`
+    struct StepGraph {
+        int64_t n;
+        int cur, end_cur;
+        bool last;
+        hipGraphExec_t exec;
+    };
+    std::vector<StepGraph> graphs;
+    bool use_graphs = true;
+    hipStream_t capture = nullptr;
+    void drop_graphs()
+    {
+        for (auto& g : graphs) ignore(hipGraphExecDestroy(g.exec));
+        graphs.clear();
+    }
 
     uint32_t n() const { return pr.n; }
     int64_t n_links() const { return pr.n_links; }
@@ -130,6 +146,8 @@ void release(lbm_ctx* c)
     if (c->h_result) ignore(hipHostFree(c->h_result));
     if (c->ev0) ignore(hipEventDestroy(c->ev0));
     if (c->ev1) ignore(hipEventDestroy(c->ev1));
+    c->drop_graphs();
+    if (c->capture) ignore(hipStreamDestroy(c->capture));
     ignore(hipSetDevice(prev));
     delete c;
 }
@@ -412,6 +430,72 @@ lbm_status lbm_init_fields_neq(lbm_ctx* c, const double* rho, const double* ux, 
     return init_fields(c, rho, ux, uy, device_ptrs, c->pr.g.tau_s);
 }
 
+// The launches of n steps from the current time level; the last launch records u(t) for
+// lbm_residual when `last` is set.
+lbm_status run_steps(lbm_ctx* c, int64_t n, bool last)
+{
+    for (int64_t it = 0; it < n;) {
+        const int64_t left = n - it;
+        lbm_status st;
+        if (c->fuse == 2 && left >= 2) {
+            st = step_pair(c, last && left == 2);
+            it += 2;
+        } else {
+            st = step_once(c, last && left == 1);
+            it += 1;
+        }
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+// n steps by replaying a captured graph of run_steps(n, last) (captured at first use on the
+// private capture stream; the host-side state is restored after capture and advanced as the
+// replay advances it).  A capture failure switches the context to eager launches for good.
+lbm_status graph_steps(lbm_ctx* c, int64_t n, bool last)
+{
+    lbm_ctx::StepGraph* g = nullptr;
+    for (auto& e : c->graphs)
+        if (e.n == n && e.cur == c->cur && e.last == last) g = &e;
+    if (!g) {
+        if (!c->capture && hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+            c->capture = nullptr;
+            c->use_graphs = false;
+            return run_steps(c, n, last);
+        }
+        if (c->graphs.size() >= 16) c->drop_graphs();
+        const int cur0 = c->cur;
+        const int64_t steps0 = c->steps;
+        hipStream_t user = c->stream;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool ok = hipStreamBeginCapture(c->capture, hipStreamCaptureModeRelaxed) == hipSuccess;
+        if (ok) {
+            c->stream = c->capture;
+            const lbm_status st = run_steps(c, n, last);
+            c->stream = user;
+            ok = hipStreamEndCapture(c->capture, &graph) == hipSuccess && st == LBM_OK && graph;
+        }
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) ignore(hipGraphDestroy(graph));
+        const int end_cur = c->cur;
+        c->cur = cur0;
+        c->steps = steps0;
+        ignore(hipGetLastError());
+        if (!ok) {
+            if (exec) ignore(hipGraphExecDestroy(exec));
+            c->use_graphs = false;
+            return run_steps(c, n, last);
+        }
+        c->graphs.push_back(lbm_ctx::StepGraph{n, cur0, end_cur, last, exec});
+        g = &c->graphs.back();
+    }
+    if (hipGraphLaunch(g->exec, c->stream) != hipSuccess) return fail(LBM_E_HIP, "step graph launch failed");
+    c->cur = g->end_cur;
+    c->steps += n;
+    return LBM_OK;
+}
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
 {
     if (!c) return fail(LBM_E_INVAL, "null context");
@@ -419,25 +503,36 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
     if (nsteps == 0) return LBM_OK;
     DeviceGuard g(c->device);
     if (c->timing) LBM_HIP_TRY(hipEventRecord(c->ev0, c->stream));
-    for (int64_t it = 0; it < nsteps;) {
-        // the last step records u(t) so that lbm_residual can compare it with u(t + 1)
-        const int64_t left = nsteps - it;
-        lbm_status st;
-        if (c->fuse == 2 && left >= 2) {
-            st = step_pair(c, left == 2);
-            it += 2;
-        } else {
-            st = step_once(c, left == 1);
-            it += 1;
+    lbm_status st = LBM_OK;
+    if (c->use_graphs && nsteps >= 4) {
+        // graphs of at most 256 steps (an even count keeps the time-level parity of every launch
+        // sequence but the last), the last one recording u
+        constexpr int64_t kGraphSteps = 256;
+        int64_t left = nsteps;
+        while (st == LBM_OK && left > kGraphSteps) {
+            st = graph_steps(c, kGraphSteps, false);
+            left -= kGraphSteps;
         }
-        if (st != LBM_OK) return st;
+        if (st == LBM_OK) st = c->use_graphs ? graph_steps(c, left, true) : run_steps(c, left, true);
+    } else {
+        st = run_steps(c, nsteps, true);
     }
+    if (st != LBM_OK) return st;
     if (c->timing) {
         LBM_HIP_TRY(hipEventRecord(c->ev1, c->stream));
         c->have_timing = true;
         c->timed_steps = nsteps;
     }
     c->uprev_valid = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graphs(lbm_ctx* c, int32_t on)
+{
+    if (!c) return fail(LBM_E_INVAL, "null context");
+    DeviceGuard g(c->device);
+    c->drop_graphs();
+    c->use_graphs = on != 0;
     return LBM_OK;
 }
 
@@ -523,6 +618,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block)
     if (lbm::step_lds_bytes(c->fp32(), links) > lbm::kMaxLds)
         return fail(LBM_E_INVAL, "block %d would stage %u wall links, more than the LDS limit", block, links);
     c->block = block;
+    c->drop_graphs();
     c->lds_links = links;
     return LBM_OK;
 }
@@ -530,6 +626,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block)
 lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows)
 {
     if (!c) return fail(LBM_E_INVAL, "null context");
+    c->drop_graphs();
     if (steps_per_launch == 1) {
         c->fuse = 1;
         return LBM_OK;

@@ -91,6 +91,7 @@ SIGNATURES = {
     "lbm_set_launch": (C.c_int32, [_VP, C.c_int32]),
     "lbm_stream_copy": (C.c_int32, [_VP, _VP, C.c_int64, _VP]),
     "lbm_set_timing": (C.c_int32, [_VP, C.c_int32]),
+    "lbm_set_graphs": (C.c_int32, [_VP, C.c_int32]),
     "lbm_set_fusion": (C.c_int32, [_VP, C.c_int32, C.c_int32]),
     "lbm_last_step_ms": (C.c_int32, [_VP, _DPTR, C.POINTER(C.c_int64)]),
     "lbm_batch_create": (C.c_int32, [C.c_int32, C.POINTER(Params), C.POINTER(_VP), C.POINTER(_VP),
@@ -314,6 +315,10 @@ class Lattice:
 
     def set_timing(self, on=True):
         _check(self._lib.lbm_set_timing(self._h, int(bool(on))))
+
+    def set_graphs(self, on=True):
+        """lbm_step by graph replay (default) or by one launch after the other."""
+        _check(self._lib.lbm_set_graphs(self._h, int(bool(on))))
 
     def last_step_ms(self):
         ms, n = C.c_double(), C.c_int64()
