@@ -9,7 +9,10 @@
 // upsamples the level below (nearest), concatenates the encoder output of level l, and applies two
 // 3x3 convolutions with ReLU.  A 1x1 convolution gives the outputs.  The encoder output of level l
 // is written straight into the second channel slice of decoder level l's concatenation buffer, so
-// the skip connection costs no copy.
+// the skip connection costs no copy; where the halo-tile kernels run, the pooling and the output 1x1
+// convolution are done in the output stage of the convolution before them, and the decoder's first
+// convolution (forward and weight gradient) reads the upsampled channels straight from the level
+// below.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
