@@ -63,6 +63,11 @@ CONV_CASES = [
     (1, 16, 32, 48, 96, 3),
     (2, 16, 64, 16, 64, 3),
     (4, 128, 128, 32, 64, 3),
+    # partial tiles: 40 output channels over 32-channel tiles (and 16-channel weight-gradient
+    # groups) with a 24-channel input; 192 output channels over 8 x 16 x 64 tiles with a short last
+    # chunk of a 40-channel input
+    (1, 16, 32, 24, 40, 3),
+    (1, 8, 16, 40, 192, 3),
 ]
 
 
