@@ -155,6 +155,8 @@ lbm_status lbm_params_comparison(lbm_params *p, int32_t scheme, double gamma_fro
  *   links    host, n_links records; every (fluid node, direction) whose neighbour is solid must
  *            appear exactly once; order is free
  *   stream   hipStream_t for all device work of this context (NULL = the null stream)
+ * Limits (LBM_E_INVAL): nx, ny >= 1, nx * ny < 2^31 sites and n_links <= 2^31 - 1, so that site
+ * indices and link offsets fit the kernels' 32-bit indices.
  * Validation (LBM_E_GEOMETRY): x_f fluid and x_f + c_dir solid, 0 < q <= 1, finite wall velocity,
  * no duplicate, no missing link, no fluid node on a non-periodic edge, no fluid node whose eight
  * neighbours are all solid.  LBM_E_PARAM: tau_s or tau_q <= 1/2, any tau <= 1/2, 1 + l <= 0 or
@@ -279,7 +281,9 @@ typedef struct {
 
 /* Creates a batch of n_inst lattices.  params[i], solids[i], links[i] (n_links[i] records) are
  * instance i's arguments of lbm_create, with the same validation; all params[i].precision and
- * params[i].diffuse must be equal (else LBM_E_INVAL).  Inputs are copied.  All instances start at
+ * params[i].diffuse must be equal (else LBM_E_INVAL).  The batch's site space (each instance's sites
+ * padded to a whole number of tiles) must stay below 2^31 sites and its wall links at most
+ * 2^31 - 1 in total (else LBM_E_INVAL).  Inputs are copied.  All instances start at
  * rest and active.  stream: hipStream_t for all work (NULL: the batch creates its own stream;
  * graphs cannot be captured on the null stream). */
 lbm_status lbm_batch_create(int32_t n_inst, const lbm_params *params, const uint8_t *const *solids,

@@ -380,6 +380,10 @@ lbm_status lbm_batch_create(int32_t n_inst, const lbm_params* params, const uint
             release(b);
             return fail(LBM_E_INVAL, "batch exceeds 2^31 sites");
         }
+        if (nl_total > INT32_MAX) {  // global link offsets in the int32 chunk table
+            release(b);
+            return fail(LBM_E_INVAL, "batch exceeds 2^31 - 1 wall links");
+        }
     }
     b->ps = uint32_t(sites);
     b->total_links = nl_total;

@@ -77,6 +77,9 @@ lbm_status prepare(const lbm_params* p, const uint8_t* solid, const lbm_link* li
                    Prepared& out)
 {
     if (!p || !solid || (n_links > 0 && !links) || n_links < 0) return fail(LBM_E_INVAL, "null or negative input");
+    // the chunk table holds link offsets as int32
+    if (n_links > INT32_MAX)
+        return fail(LBM_E_INVAL, "%lld wall links exceed 2^31 - 1", (long long)n_links);
     if (p->nx <= 0 || p->ny <= 0) return fail(LBM_E_INVAL, "lattice size %d x %d", p->nx, p->ny);
     const uint64_t n64 = uint64_t(p->nx) * uint64_t(p->ny);
     if (n64 >= (uint64_t(1) << 31))

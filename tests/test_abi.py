@@ -143,6 +143,22 @@ def test_null_and_size_errors():
     assert lib.lbm_get_info(None, None) == -1
 
 
+def test_index_width_limits():
+    """Lattices of 2^31 sites or more, and more than 2^31 - 1 wall links, are refused before any
+    input is read (the kernels index sites and link offsets in 32 bits)."""
+    lib = lbm.load()
+    solid = np.ascontiguousarray(BASE["solid"], np.uint8)
+    links, n = lbm.make_links(BASE["links"])
+    h = C.c_void_p()
+    p = lbm.make_params(dict(BASE["params"]), solid.shape)
+    p.nx, p.ny = 1 << 16, 1 << 15  # 2^31 sites: refused on the size alone
+    assert lib.lbm_create(C.byref(p), solid.ctypes.data_as(C.c_void_p), links, n, None, C.byref(h)) == -1
+    assert "2^31" in lib.lbm_last_error().decode() and not h.value
+    p = lbm.make_params(dict(BASE["params"]), solid.shape)  # valid, but a link count past int32 offsets
+    assert lib.lbm_create(C.byref(p), solid.ctypes.data_as(C.c_void_p), links, 1 << 31, None, C.byref(h)) == -1
+    assert "2^31 - 1" in lib.lbm_last_error().decode() and not h.value
+
+
 def test_batch_validation_errors():
     """Batch creation validates every instance on the host and names the failing one."""
     lib = lbm.load()
