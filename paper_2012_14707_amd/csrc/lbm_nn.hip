@@ -1164,7 +1164,7 @@ __global__ void __launch_bounds__(256) k_mask_count(const uint8_t* mask, int P, 
     sh[threadIdx.x] = (p < P && mask[p]) ? 1.f : 0.f;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
@@ -1179,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_sum_partials(const float* part, int n, 
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = sh[0];
@@ -1209,7 +1209,7 @@ __global__ void __launch_bounds__(256) k_mse(const float* y, const float* t, con
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
