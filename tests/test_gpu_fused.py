@@ -1,7 +1,8 @@
 """Two time steps per launch (temporal blocking, lbm_set_fusion): bit-identical to one step per
 launch on lattices that tile into 64 x rows blocks, for both storage precisions, every tile-row
 option, odd step counts (pairs plus a single step) and moving walls; lattices that do not tile
-keep one step per launch; both readings of the diffuse term and chunks with more link entries than a wave holds are covered."""
+keep one step per launch; both readings of the diffuse term, chunks with more link entries than a
+wave holds, a lattice without walls and wholly solid tiles are covered."""
 import sys
 
 import numpy as np
@@ -35,6 +36,24 @@ def _problem(case):
         # 64 x 64 tiles of 64 x 4 (64 x 32 of 64 x 8): fp32 launches walk them in the banded per-XCD
         # order, which remaps most tiles here (test_banded_tile_order_remaps_this_lattice)
         return G.random_cylinders(n=4096, ny=256, porosity=0.75, rmin=5, rmax=14, seed=6, kn=0.02, h=20.0, ax=2e-6)
+    if case == "box128x16":
+        # fully periodic, no walls: every tile's link range is empty
+        return dict(params=G.base_params(periodic_x=1, periodic_y=1, tau_s_override=0.8, tau_q_override=1.1,
+                                         ax=1e-5, ay=-2e-6),
+                    solid=np.zeros((16, 128), np.uint8), links=G._empty_links(), meta=dict(kind="box"))
+    if case == "slab128x32":
+        # periodic channel whose wall is a 12-row solid slab with a ragged face: whole 64 x 4 and
+        # 64 x 8 tiles are solid (no site of theirs is loaded, collided or stored)
+        s = np.zeros((32, 128), np.uint8)
+        s[8:20] = 1
+        x = np.arange(128)
+        s[7, (x % 5) == 0] = 1
+        s[20, (x % 7) == 3] = 1
+        xs, ys, ds = G.wall_candidates(s, 1, 1)
+        q = np.random.default_rng(7).uniform(0.05, 1.0, len(xs))
+        return dict(params=G.base_params(periodic_x=1, periodic_y=1, kn=0.05, h=18.0, ax=2e-6), solid=s,
+                    links=dict(x=xs, y=ys, dir=ds, q=q, ubx=np.zeros(len(xs)), uby=np.zeros(len(xs))),
+                    meta=dict(kind="slab"))
     if case == "channel64":
         return G.channel(30, nx=64, gamma=0.37, kn=0.05, ax=1e-6, u_top=0.01)
     if case == "annulus128":
@@ -59,7 +78,7 @@ def _same(a, b):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", ["cylinders256", "cylinders128x192", "cylinders2048x128", "cylinders4096x256",
-                                  "channel64", "annulus128"])
+                                  "channel64", "annulus128", "box128x16", "slab128x32"])
 def test_two_step_launch_bitwise(case, precision):
     from paper_2012_14707_amd import lbm
     pb = _problem(case)

@@ -227,6 +227,25 @@ def test_ragged_small_lattices():
         compare(pb, 50, "fp64", init=(np.full(shape, 1.02), np.full(shape, 1e-3), np.zeros(shape)))
 
 
+def test_wall_free_and_wholly_solid_tiles():
+    """Two-step tiles with no wall link at all (a fully periodic box) and tiles that are wholly solid
+    (a channel bounded by a thick slab with a ragged face), against the oracle; solid sites report
+    zero moments."""
+    from tests.test_gpu_fused import _problem
+    for case, steps in (("box128x16", 300), ("slab128x32", 600)):
+        pb = _problem(case)
+        for precision in ("fp64", "fp32"):
+            init = None
+            if case == "box128x16":  # a decaying shear wave on top of the forcing
+                y = np.arange(16)[:, None] * np.ones((1, 128))
+                init = (np.ones((16, 128)), 1e-3 * np.sin(2 * np.pi * y / 16), np.zeros((16, 128)))
+            lat, _, _ = compare(pb, steps, precision, init=init)
+            assert lat.info["steps_per_launch"] == 2
+            rho, ux, uy = lat.moments_host()
+            solid = pb["solid"] != 0
+            assert not rho[solid].any() and not ux[solid].any() and not uy[solid].any()
+
+
 def test_config1_fp32_and_modes():
     pb = G.poiseuille_config1()
     compare(pb, 1100, "fp32")
