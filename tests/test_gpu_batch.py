@@ -25,6 +25,7 @@ def _say(*a):
 
 
 def _problems():
+    from tests.test_gpu_fused import _problem
     ragged = np.zeros((23, 37), np.uint8)
     ragged[0], ragged[-1] = 1, 1
     yy, xx = np.mgrid[0:23, 0:37]
@@ -40,6 +41,9 @@ def _problems():
         rag,
         G.random_cylinders(n=256, porosity=0.7, rmin=8, rmax=24, seed=11, kn=0.05, h=32.0, ax=1e-6),
         G.channel(300, nx=4, gamma=0.77, kn=0.02, ax=2e-7),
+        # no wall link at all, and wholly solid tiles (rows 8-19 of the slab: 1536 sites)
+        _problem("box128x16"),
+        _problem("slab128x32"),
     ]
 
 
