@@ -63,7 +63,7 @@ struct ConvArgs {
     int kper;           // split K: K range of one split (a multiple of TK)
     Slice pool;         // 2x2 mean of the bf16 output at H/2 x W/2 (p null: none; halo-tile kernel only)
     // a 1x1 convolution of the bf16 output (all Cout = 32 channels) into y1, fp32 [pixels][c1]
-    // (w1 [c1][32], b1 [c1] or null; w1 null: none; 16 x 32 x 32 halo tiles only)
+    // (w1 [c1][32], b1 [c1] or null; w1 null: none; 8 x 32 x 32 halo tiles only)
     const bf16* w1;
     const float* b1;
     float* y1;
@@ -458,11 +458,14 @@ __device__ __forceinline__ void tile_epilogue(const ConvArgs& a, const f4 (&acc)
 // per barrier: the K step of the pixel-row kernel above gives 4-8, too few to cover the load
 // latency and the barrier.  Waves form a WR x (4 / WR) grid over tile rows x output channels; a
 // wave reads each halo-row window once and applies it to up to three of its output rows.  NS
-// stages (2: the next chunk's direct loads are issued right after the barrier; 1: single chunk).
+// stages: 2, the next chunk's direct loads are issued right after the barrier; 1, they are issued
+// after the chunk's multiplies, behind a second barrier (half the LDS, so more blocks per CU overlap
+// one block's loads with the others' multiplies).  ONE: the block's K is a single chunk (no reload
+// code, whose live source addresses would cost registers).
 // Thread t fills the 16-byte slots 256 j + t of each stage (the lane order of its wave's direct
 // loads); a slot's row and K group fix the source address, which is set once and then advanced
 // by the chunk offset (the fifth slot of a row, padding, loads zeros).
-template <int TH, int TW, int BN, int WR, int NS>
+template <int TH, int TW, int BN, int WR, int NS, bool ONE>
 __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
 {
     constexpr int WC = 4 / WR, RW = TH / WR, CW = BN / WC, CG = TW / 16, NJ = CW / 16;
@@ -471,6 +474,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
     constexpr int SA = JA * 256, SS = SA + JB * 256;  // 16-byte slots: input part, one stage
     static_assert(WR * WC == 4 && RW * WR == TH && CW * WC == BN && NJ * 16 == CW && CG * 16 == TW, "tile shape");
     static_assert(NS == 1 || NS == 2, "one or two stages");
+    static_assert(!(ONE && NS == 2), "a single chunk needs one stage");
     static_assert(NS * SS * 16 <= 163840, "LDS");
     __shared__ __align__(16) bf16x8 lds[NS * SS];
     const int tid = threadIdx.x, lane = tid % 64;
@@ -480,7 +484,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
     const int y0 = ty * TH, x0 = tx * TW, n0 = blockIdx.y * BN;
     const int c_begin = a.part ? blockIdx.z * a.kper : 0;
     const int c_end = a.part ? min(a.Cin, c_begin + a.kper) : a.Cin;
-    const int nsteps = (c_end - c_begin + TK - 1) / TK;
+    const int nsteps = ONE ? 1 : (c_end - c_begin + TK - 1) / TK;
     const bf16* zero = g_zero;
     // slot 256 j + t: row (256 j + t) / 5, K group (256 j + t) % 5 (4: padding)
     const bf16* asrc[JA];
@@ -599,6 +603,13 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
                     }
                 }
         asm volatile("" ::: "memory");
+        if (NS == 1 && !ONE && s + 1 < nsteps) {
+            // one stage: every wave has read this chunk before the next one overwrites it
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            issue(s + 1);
+        }
     }
 
     tile_epilogue<TH, TW, BN, WR, NS * SS * 16>(a, acc, lds, n, y0, x0, n0, wr, wc, lane, tid);
@@ -1378,12 +1389,14 @@ int row_splits(long P, int Cin, int Cout, int taps)
 // Kernel and K split of one forward convolution.  3x3 convolutions whose image is a whole number
 // of tiles take the halo-tile kernel: 8 x 32 pixels x 64 channels when the output channels are a
 // multiple of 64 and that still gives a block per compute unit (256), else 8 x 16 x 64, else
-// 16 x 32 x 32 (8 x 32 x 32 for a single input chunk: three blocks per CU overlap one block's loads
-// with the others' multiplies, measured 2-6% faster on the 256^2 x 32-channel layers); K is split
-// (over the workspace) when the grid has fewer than 256 blocks, at most 8 ways and, with four or
-// more chunks, at least two 32-channel chunks per split.
+// 8 x 32 x 32.  K is split (over the workspace) when the grid has fewer than 256 blocks, at most 8
+// ways and, with four or more chunks, at least two 32-channel chunks per split.  Measured at batch 8
+// on 256^2: small tiles that put several blocks on a CU beat larger ones (8 x 32 x 32 with one
+// reloaded LDS stage, three blocks per CU: 48 us for 96 -> 32 channels against 69 us for
+// 16 x 32 x 32 tiles with two stages, one block per CU; 2-6% on the single-chunk 32-channel
+// layers), while 8 x 16 x 64 tiles in place of 8 x 32 x 64 ones at 64^2 gained nothing.
 struct FwdPlan {
-    int kind;    // 0: pixel-row kernel; 1: tiles 16 x 32 x 32; 2: 8 x 32 x 64; 3: 8 x 16 x 64; 4: 8 x 32 x 32
+    int kind;    // 0: pixel-row kernel; halo tiles 1: 8 x 32 x 64; 2: 8 x 16 x 64; 3: 8 x 32 x 32
     int splits;  // K splits, 1: none
     int kper;    // K per split: input channels (tiles) or (tap, channel) positions (pixel rows)
 };
@@ -1396,18 +1409,13 @@ FwdPlan fwd_plan(int N, int H, int W, int Cin, int Cout, int taps)
         auto nb = [&](int th, int tw, int bn) { return long(N) * (H / th) * (W / tw) * ((Cout + bn - 1) / bn); };
         long blocks = 0;
         if (Cout % 64 == 0 && H % 8 == 0 && W % 32 == 0 && nb(8, 32, 64) >= 256) {
-            f.kind = 2;
+            f.kind = 1;
             blocks = nb(8, 32, 64);
         } else if (Cout % 64 == 0 && H % 8 == 0 && W % 16 == 0) {
-            f.kind = 3;
+            f.kind = 2;
             blocks = nb(8, 16, 64);
-        } else if (H % 16 == 0 && W % 32 == 0 && Cin > TK) {
-            f.kind = 1;
-            blocks = nb(16, 32, 32);
         } else if (H % 8 == 0 && W % 32 == 0) {
-            // one input chunk: smaller tiles, three blocks per CU, so that one block's loads overlap
-            // the others' multiplies
-            f.kind = 4;
+            f.kind = 3;
             blocks = nb(8, 32, 32);
         }
         if (f.kind) {
@@ -1437,10 +1445,16 @@ template <int TH, int TW, int BN, int WR>
 void launch_tile(const ConvArgs& a, int nsplit, int chunks_per_block, hipStream_t st)
 {
     const dim3 grid(unsigned(a.N * (a.H / TH) * (a.W / TW)), unsigned((a.Cout + BN - 1) / BN), unsigned(nsplit));
-    if (chunks_per_block > 1)
-        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 2>), grid, dim3(256), 0, st, a);
+    // several chunks: one reloaded stage where the grid puts two or more blocks on each CU (half
+    // the LDS lets them share it: 53-78 KB per block), else two stages, so that a lone block still
+    // overlaps its next chunk's loads with its multiplies
+    const long nblocks = long(grid.x) * grid.y * grid.z;
+    if (chunks_per_block == 1)
+        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 1, true>), grid, dim3(256), 0, st, a);
+    else if (nblocks >= 512)
+        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 1, false>), grid, dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 1>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, WR, 2, false>), grid, dim3(256), 0, st, a);
 }
 
 // pool.p non-null: also the 2x2 mean of the bf16 output y (H and W even) into pool, fused into the
@@ -1527,7 +1541,7 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         // fused pooling needs the staged bf16 output stage of an unsplit tile launch
         const bool staged = !split && y.p && Cout % 8 == 0 && y.cs % 8 == 0 && y.co % 8 == 0;
         const bool fuse_pool = pool.p && staged;
-        const bool fuse_1x1 = o1.w && staged && (f.kind == 1 || f.kind == 4) && Cout == 32 && o1.c <= 16;
+        const bool fuse_1x1 = o1.w && staged && f.kind == 3 && Cout == 32 && o1.c <= 16;
         if (fuse_pool) a.pool = pool;
         if (fuse_1x1) {
             a.w1 = o1.w;
@@ -1535,9 +1549,8 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
             a.y1 = o1.y;
             a.c1 = o1.c;
         }
-        if (f.kind == 1) launch_tile<16, 32, 32, 4>(a, nsplit, chunks, st);
-        else if (f.kind == 2) launch_tile<8, 32, 64, 2>(a, nsplit, chunks, st);
-        else if (f.kind == 3) launch_tile<8, 16, 64, 2>(a, nsplit, chunks, st);
+        if (f.kind == 1) launch_tile<8, 32, 64, 2>(a, nsplit, chunks, st);
+        else if (f.kind == 2) launch_tile<8, 16, 64, 2>(a, nsplit, chunks, st);
         else launch_tile<8, 32, 32, 4>(a, nsplit, chunks, st);
         if (split) hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
         if (!fuse_pool) {

@@ -57,12 +57,21 @@ CONV_CASES = [
     (2, 16, 16, 512, 64, 3),
     (2, 19, 11, 96, 32, 1),
     (1, 32, 32, 32, 8, 1),
-    # 3x3 halo tiles: 16 x 32 x 32 with one chunk, with a short last chunk and three channel tiles;
+    # 3x3 halo tiles: 8 x 32 x 32 with one chunk, with a short last chunk and three channel tiles;
     # 8 x 16 x 64 with a short single chunk; 8 x 32 x 64 (enough blocks at batch 4)
     (2, 32, 64, 32, 32, 3),
     (1, 16, 32, 48, 96, 3),
     (2, 16, 64, 16, 64, 3),
     (4, 128, 128, 32, 64, 3),
+    # tiles over several chunks: two LDS stages below 512 blocks (8 x 32 x 32 with a short last
+    # chunk; two chunks per split of two), one reloaded stage from 512 blocks on (8 x 32 x 32 with
+    # three chunks and with a short last chunk, 8 x 32 x 64, 8 x 16 x 64)
+    (4, 64, 256, 40, 32, 3),
+    (2, 64, 256, 96, 32, 3),
+    (8, 64, 256, 96, 32, 3),
+    (8, 64, 256, 40, 32, 3),
+    (8, 64, 256, 64, 64, 3),
+    (8, 64, 144, 64, 64, 3),
     # partial tiles: 40 output channels over 32-channel tiles (and 16-channel weight-gradient
     # groups) with a 24-channel input; 192 output channels over 8 x 16 x 64 tiles with a short last
     # chunk of a 40-channel input
