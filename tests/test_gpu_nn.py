@@ -163,6 +163,26 @@ def _net_inputs(rng, n, h, w, cin, cout):
     return x, target, mask
 
 
+def _seeded_net(rng, L, base, cin, cout, h, w, max_batch, periodic):
+    """A network with the device's seeded weights and random non-zero biases (so that they are
+    exercised); returns it with its parameters as the oracle takes them."""
+    from paper_2012_14707_amd import lbm
+    net = lbm.Net(levels=L, base_channels=base, in_channels=cin, out_channels=cout, height=h, width=w,
+                  max_batch=max_batch, periodic=periodic, seed=5)
+    assert net.n_params == U.param_count(L, base, cin, cout)
+    flat = net.get_params().astype(np.float64)
+    # the device's seeded initialisation: padded input columns and output rows are zero
+    ws = U.unpack(flat, L, base, cin, cout)
+    assert np.all(ws[0][0].numpy()[:, :, cin:] == 0) and np.all(ws[-1][0].numpy()[:, cout:, :] == 0)
+    off = 0
+    for t, ci, co in U.layer_shapes(L, base, cin, cout):
+        off += t * ci * co
+        flat[off:off + co] = rng.normal(scale=0.05, size=co) * (np.arange(co) < (cout if co == 8 and t == 1 else co))
+        off += co
+    net.set_params(flat.astype(np.float32))
+    return net, flat.astype(np.float32).astype(np.float64)
+
+
 # (levels, base channels, in, out, batch, height, width, periodic).  The 256^2 network at batch 1
 # splits K in most deep layers (pooling and upsampling then take their separate passes below level
 # 0); at batch 4 levels 1 and 2 run unsplit with the pooling fused into the convolutions, here with
@@ -175,22 +195,7 @@ def test_network_forward_and_gradients(shape):
     L, base, cin, cout, n, h, w, periodic = shape
     _say(f"[net] {shape}")
     rng = np.random.default_rng(L * 100 + base)
-    net = lbm.Net(levels=L, base_channels=base, in_channels=cin, out_channels=cout, height=h, width=w,
-                  max_batch=max(n, 2), periodic=periodic, seed=5)
-    assert net.n_params == U.param_count(L, base, cin, cout)
-    flat = net.get_params().astype(np.float64)
-    # the device's seeded initialisation: padded input columns and output rows are zero
-    ws = U.unpack(flat, L, base, cin, cout)
-    assert np.all(ws[0][0].numpy()[:, :, cin:] == 0) and np.all(ws[-1][0].numpy()[:, cout:, :] == 0)
-    # give the biases non-zero values so that they are exercised
-    flat = flat + 0.0
-    off = 0
-    for t, ci, co in U.layer_shapes(L, base, cin, cout):
-        off += t * ci * co
-        flat[off:off + co] = rng.normal(scale=0.05, size=co) * (np.arange(co) < (cout if co == 8 and t == 1 else co))
-        off += co
-    net.set_params(flat.astype(np.float32))
-    flat = flat.astype(np.float32).astype(np.float64)
+    net, flat = _seeded_net(rng, L, base, cin, cout, h, w, max(n, 2), periodic)
     x, target, mask = _net_inputs(rng, n, h, w, cin, cout)
     y = torch.empty((n, h, w, cout), dtype=torch.float32, device="cuda")
     net.forward(_dev_bf16(x), y)
@@ -227,6 +232,30 @@ def test_network_forward_and_gradients(shape):
     for st in stats:
         assert st[1] is None or (st[3] >= 0.9999 and st[4] <= 2e-2 and st[1] >= 0.998), st
     _say(f"[net] {shape}: worst gradient cosine {worst:.6f}")
+    net.close()
+
+
+def test_network_forward_at_the_benchmark_batch():
+    """The warm-start network's shape at batch 8, the configuration the benchmark times (its plans
+    differ from smaller batches: one reloaded LDS stage at 256^2 and 128^2, no K splits above the
+    deepest level), against the oracle network."""
+    import torch
+    from paper_2012_14707_amd import warmstart as W
+    shape = W.NET_SHAPE
+    L, base, cin, cout = shape["levels"], shape["base_channels"], shape["in_channels"], shape["out_channels"]
+    n, h, w, periodic = 8, W.SIDE, W.SIDE, True
+    rng = np.random.default_rng(8)
+    net, flat = _seeded_net(rng, L, base, cin, cout, h, w, n, periodic)
+    x, _, _ = _net_inputs(rng, n, h, w, cin, cout)
+    y = torch.empty((n, h, w, cout), dtype=torch.float32, device="cuda")
+    net.forward(_dev_bf16(x), y)
+    got = y.cpu().numpy().astype(np.float64)
+    emu = U.forward(x, flat, L, base, cin, cout, emulate_bf16=True, periodic=periodic).numpy()
+    exact = U.forward(x, flat, L, base, cin, cout, periodic=periodic).numpy()
+    e_emu = np.abs(got - emu).max() / np.abs(emu).max()
+    e_ex = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+    _say(f"[net] batch {n}: forward err vs emulated {e_emu:.2e}, vs exact {e_ex:.2e}")
+    assert e_emu <= 1e-2 and e_ex <= 5e-2
     net.close()
 
 
