@@ -35,6 +35,7 @@ namespace nn {
 
 typedef __bf16 bf16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f4;
 
 // ------------------------------------------------------------------------ matrix-core GEMMs
@@ -615,6 +616,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(const ConvArgs a)
     tile_epilogue<TH, TW, BN, WR, NS * SS * 16>(a, acc, lds, n, y0, x0, n0, wr, wc, lane, tid);
 }
 
+// Split-K epilogue: y = act(bias + sum over k of part[k]), partials summed in split order.
 __global__ void __launch_bounds__(256) k_split_sum(const ConvArgs a, int splits)
 {
     const size_t P = size_t(a.N) * a.H * a.W;
@@ -629,6 +631,44 @@ __global__ void __launch_bounds__(256) k_split_sum(const ConvArgs a, int splits)
     if (a.relu) v = fmaxf(v, 0.f);
     if (a.y.p) a.y.p[row * a.y.cs + a.y.co + col] = bf16(v);
     if (a.yf) a.yf[e] = v;
+}
+
+// The same for four consecutive channels per thread (Cout, the output slice and the fp32 output
+// aligned to four elements): 16-byte partial loads, the same sums in the same order.
+__global__ void __launch_bounds__(256) k_split_sum4(const ConvArgs a, int splits)
+{
+    const size_t P = size_t(a.N) * a.H * a.W, n = P * a.Cout;
+    const size_t e = 4 * (size_t(blockIdx.x) * 256 + threadIdx.x);
+    if (e >= n) return;
+    const int col = int(e % a.Cout);
+    const size_t row = e / a.Cout;
+    f4 s = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < splits; ++k) s += *reinterpret_cast<const f4*>(a.part + size_t(k) * n + e);
+    f4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (a.bias ? a.bias[col + i] : 0.f) + s[i];
+        if (a.relu) v[i] = fmaxf(v[i], 0.f);
+    }
+    if (a.y.p) {
+        bf16x4 o;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = bf16(v[i]);
+        *reinterpret_cast<bf16x4*>(a.y.p + row * a.y.cs + a.y.co + col) = o;
+    }
+    if (a.yf) *reinterpret_cast<f4*>(a.yf + e) = v;
+}
+
+void split_sum(const ConvArgs& a, int splits, hipStream_t st)
+{
+    const size_t n = size_t(a.N) * a.H * a.W * a.Cout;
+    const bool vec = a.Cout % 4 == 0 && a.y.cs % 4 == 0 && a.y.co % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(a.y.p) % 8 == 0 && reinterpret_cast<uintptr_t>(a.yf) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(a.part) % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_split_sum4, dim3(unsigned((n / 4 + 255) / 256)), dim3(256), 0, st, a, splits);
+    else
+        hipLaunchKernelGGL(k_split_sum, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, a, splits);
 }
 
 struct WgradArgs {
@@ -857,7 +897,6 @@ __global__ void __launch_bounds__(256) k_wgrad_tile(const WgradArgs a)
     };
 
     typedef __attribute__((address_space(3))) __bf16 lbf16;
-    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(3))) bf16x4 lbf16x4;
     auto tr = [&](const lbf16* p) __attribute__((always_inline)) {
         return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lbf16x4*)p);
@@ -1552,7 +1591,7 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
         if (f.kind == 1) launch_tile<8, 32, 64, 2>(a, nsplit, chunks, st);
         else if (f.kind == 2) launch_tile<8, 16, 64, 2>(a, nsplit, chunks, st);
         else launch_tile<8, 32, 32, 4>(a, nsplit, chunks, st);
-        if (split) hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
+        if (split) split_sum(a, nsplit, st);
         if (!fuse_pool) {
             const hipError_t e = pool_pass();
             if (e != hipSuccess) return e;
@@ -1566,7 +1605,7 @@ hipError_t conv_forward(CSlice x, const bf16* w, const float* bias, Slice y, flo
             hipLaunchKernelGGL((k_conv_fwd<9, 64, 64, kConvStages>), grid, dim3(256), lds, st, a);
         else
             hipLaunchKernelGGL((k_conv_fwd<1, 64, 64, kConvStages>), grid, dim3(256), lds, st, a);
-        hipLaunchKernelGGL(k_split_sum, dim3(blocks(size_t(P) * Cout)), dim3(256), 0, st, a, nsplit);
+        split_sum(a, nsplit, st);
         const hipError_t e = pool_pass();
         return e != hipSuccess ? e : out1_pass();
     }
